@@ -1,0 +1,273 @@
+"""Physics pins for the oracle's time stepping.
+
+* Homogeneous-medium traces against the closed-form 2D/3D Green's functions
+  (paper, "Verification of numerical implementation": comparison with the
+  analytic solution, error two orders below the amplitude).  A one-step shift
+  in which wavelet sample drives which step, a missing cell-volume factor or a
+  wrong velocity scaling fails these.
+* Second-order convergence in time and convergence of manufactured solutions
+  (paper, same section: O(dt^2) in time; the variable-density manufactured
+  solution with Dirichlet sides).
+* Discrete energy conservation without damping and decay with damping.
+* Source-receiver reciprocity, mirror symmetry, density-scale invariance.
+"""
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+
+import oracle
+from oracle import coeffs
+from tests._analytic import (X, T, greens_2d, greens_3d, lambdify_space, grid_coords,
+                             mms_forcing)
+
+
+def _homogeneous_trace(ndim, h, so, c=1500.0, f=15.0, L=None, tf=None, R=None, shift=0):
+    L = L or (1200.0 if ndim == 2 else 600.0)
+    tf = tf or (0.35 if ndim == 2 else 0.25)
+    R = R or (150.0 if ndim == 2 else 100.0)
+    n = int(round(L / h)) + 1
+    dt = 0.5 * coeffs.critical_dt((h,) * ndim, so, c)
+    nt = int(round(tf / dt))
+    prob = oracle.Problem(n=(n,) * ndim, h=(h,) * ndim, space_order=so, dt=dt, nsteps=nt)
+    st = oracle.prepare(prob, np.full((n,) * ndim, c))
+    centre = (L / 2,) * ndim
+    recpos = (L / 2 + 0.6 * R, L / 2 + 0.8 * R) + (L / 2,) * (ndim - 2)
+    src = oracle.geometry_table(prob, [centre])
+    rec = oracle.geometry_table(prob, [recpos])
+    fw = oracle.forward(st, oracle.ricker(f, dt, nt)[:, None], src, rec, 1)
+    times = (np.arange(nt) + 1 + shift) * dt     # trace sample n is level n+1
+    ref = (greens_2d if ndim == 2 else greens_3d)(R, c, f, times, 1.0 / f)
+    return np.linalg.norm(fw.traces[:, 0] - ref) / np.linalg.norm(ref)
+
+
+def test_greens_function_2d():
+    assert _homogeneous_trace(2, 5.0, 8) < 1e-2
+
+
+def test_greens_function_3d():
+    assert _homogeneous_trace(3, 10.0, 8) < 1.5e-2
+
+
+def test_greens_function_detects_one_step_shift():
+    assert _homogeneous_trace(2, 5.0, 8, shift=1) > 5e-2
+
+
+def test_greens_function_error_falls_under_refinement():
+    e10 = _homogeneous_trace(2, 10.0, 4)
+    e5 = _homogeneous_trace(2, 5.0, 4)
+    assert e5 < 0.45 * e10
+
+
+def test_time_convergence_second_order():
+    # Same grid, dt halved three times; the Richardson differences of the
+    # final field fall by ~4 per halving.
+    n, h, so, c = 81, 10.0, 8, 2000.0
+    T_end = 0.2
+    fields = []
+    for nt in (200, 400, 800):
+        dt = T_end / nt
+        assert dt < coeffs.critical_dt((h, h), so, c)
+        prob = oracle.Problem(n=(n, n), h=(h, h), space_order=so, dt=dt, nsteps=nt)
+        st = oracle.prepare(prob, np.full((n, n), c))
+        src = oracle.geometry_table(prob, [(400.0, 400.0)])
+        rec = oracle.geometry_table(prob, [(400.0, 500.0)])
+        fields.append(oracle.forward(st, oracle.ricker(12.0, dt, nt)[:, None], src, rec, 1).p)
+    d1 = np.linalg.norm(fields[0] - fields[1])
+    d2 = np.linalg.norm(fields[1] - fields[2])
+    assert 1.85 < math.log2(d1 / d2) < 2.15
+
+
+def _mms_run(scheme, so, h, c, u_expr, rho_expr, bc, L, tf, dt, receiver=None):
+    """Relative error against the manufactured solution: the whole trace at an
+    on-grid receiver if one is given, else the whole field at the last level."""
+    n = int(round(L / h)) + 1
+    shape = (n, n)
+    nt = int(round(tf / dt))
+    prob = oracle.Problem(n=shape, h=(h, h), space_order=so, dt=dt, nsteps=nt, scheme=scheme,
+                          bc=(bc, bc))
+    coords = grid_coords(shape, (h, h))
+    rho = lambdify_space(rho_expr, 2)(*coords)
+    st = oracle.prepare(prob, np.full(shape, c), None if scheme == "const" else rho)
+    f_expr = mms_forcing(u_expr, rho_expr, c, 2)
+    f_fn = sp.lambdify((X[0], X[1], T), f_expr, "numpy")
+    u_fn = sp.lambdify((X[0], X[1], T), u_expr, "numpy")
+
+    def forcing(k):
+        return np.broadcast_to(f_fn(coords[0], coords[1], k * dt), shape)
+
+    rec_pts = [receiver] if receiver is not None else []
+    fw = oracle.forward(st, None, oracle.geometry_table(prob, []),
+                        oracle.geometry_table(prob, rec_pts, "linear"), len(rec_pts),
+                        forcing=forcing)
+    if receiver is not None:
+        t = (np.arange(nt) + 1) * dt
+        exact = np.array([u_fn(receiver[0], receiver[1], tk) for tk in t])
+        return np.linalg.norm(fw.traces[:, 0] - exact) / np.linalg.norm(exact)
+    exact = np.broadcast_to(u_fn(coords[0], coords[1], nt * dt), shape)
+    return np.max(np.abs(fw.p - exact)) / np.max(np.abs(exact))
+
+
+def _bump(L):
+    x0, x1 = X[0], X[1]
+    return sp.sin(sp.pi * x0 / L) ** 8 * sp.sin(sp.pi * x1 / L) ** 8
+
+
+@pytest.mark.parametrize("scheme", ["vd_staggered", "vd_centred", "const"])
+def test_manufactured_solution_strong_density(scheme):
+    # Compact bump (vanishes to high order at the sides, so the zero ghost
+    # condition is exact to high order) and a density varying by a factor 3.
+    L, c, so = 440.0, 2000.0, 8
+    w = 2 * math.pi * 10.0
+    errs = []
+    for h in (20.0, 10.0):
+        dt = 0.5 * coeffs.critical_dt((h, h), so, c) / 2.0
+        u = _bump(L) * sp.sin(w * T) * sp.sin(w * (T + dt))
+        rho = (2 + sp.sin(sp.pi * X[0] / L)) * (2 + sp.sin(sp.pi * X[1] / L)) \
+            if scheme != "const" else sp.Integer(1)
+        errs.append(_mms_run(scheme, so, h, c, u, rho, ("none", "none"), L, 0.075, dt))
+    assert errs[1] < 1e-3
+    assert math.log2(errs[0] / errs[1]) > 1.8, errs
+
+
+@pytest.mark.parametrize("so", [2, 4])
+def test_paper_manufactured_solution(so):
+    # The paper's variable-density verification: 440 m square, c = 2 km/s,
+    # rho = (1000 + sin(pi x/440)) (1000 + sin(pi z/440)), Dirichlet sides,
+    # u* = sin sin sin(20 pi t) sin(20 pi (t + dt)), dt = 0.05 ms, receiver at
+    # (280, 280).  Shortened to 50 ms; the error falls at the space order
+    # (at SO4 dt is cut to 0.01 ms so the time error stays below it).
+    L, c = 440.0, 2000.0
+    dt = 5e-5 if so == 2 else 1e-5
+    rho = (1000 + sp.sin(sp.pi * X[1] / L)) * (1000 + sp.sin(sp.pi * X[0] / L))
+    u = sp.sin(sp.pi * X[0] / L) * sp.sin(sp.pi * X[1] / L) * \
+        sp.sin(20 * sp.pi * T) * sp.sin(20 * sp.pi * (T + dt))
+    errs = [_mms_run("vd_centred", so, h, c, u, rho, ("dirichlet", "dirichlet"), L, 0.05, dt,
+                     receiver=(280.0, 280.0)) for h in (40.0, 20.0)]
+    assert math.log2(errs[0] / errs[1]) > so - 0.3, errs
+
+
+def test_neumann_manufactured_solution():
+    L, c, so, dt = 440.0, 2000.0, 2, 5e-5
+    u = sp.cos(sp.pi * X[0] / L) * sp.cos(sp.pi * X[1] / L) * \
+        sp.sin(20 * sp.pi * T) * sp.sin(20 * sp.pi * (T + dt))
+    errs = [_mms_run("const", so, h, c, u, sp.Integer(1), ("neumann", "neumann"), L, 0.05, dt,
+                     receiver=(120.0, 80.0)) for h in (40.0, 20.0)]
+    assert math.log2(errs[0] / errs[1]) > 1.7, errs
+
+
+def _energy_series(scheme, nbl, nt=260, n_off=40):
+    n, h, so = 61, 10.0, 8
+    rng = np.random.default_rng(7)
+    c = 1800.0 + 400.0 * rng.random((n, n))
+    rho = 1.0 + 1.5 * rng.random((n, n)) if scheme != "const" else None
+    dt = 0.5 * coeffs.critical_dt((h, h), so, c.max())
+    prob = oracle.Problem(n=(n, n), h=(h, h), space_order=so, dt=dt, nsteps=nt, scheme=scheme,
+                          nbl=((nbl, nbl), (nbl, nbl)))
+    st = oracle.prepare(prob, c, rho)
+    wav = oracle.ricker(20.0, dt, nt)
+    wav[n_off:] = 0.0
+    src = oracle.geometry_table(prob, [(301.0, 297.0)])
+    fw = oracle.forward(st, wav[:, None], src, oracle.geometry_table(prob, []), 0, keep_history=True)
+    Mc = st.K      # dt^2 c^2, or dt^2 rho c^2 for the staggered operator
+    E = []
+    for k in range(n_off + 1, nt):
+        u0, u1 = fw.history[k], fw.history[k + 1]
+        du = u1 - u0
+        E.append(np.sum(du * du / Mc) - np.sum(u1 * oracle.apply_L(st, u0)))
+    return np.array(E)
+
+
+@pytest.mark.parametrize("scheme", ["const", "vd_staggered"])
+def test_energy_conserved_without_damping(scheme):
+    E = _energy_series(scheme, 0)
+    assert np.max(np.abs(E - E[0])) < 1e-11 * abs(E[0])
+
+
+def test_energy_decays_with_damping():
+    E = _energy_series("const", 20, nt=400)
+    assert np.all(np.diff(E) <= 1e-12 * E[0])
+    assert E[-1] < 0.5 * E[0]
+
+
+def _pair_traces(scheme, a, b, interp, nbl=10):
+    n, h, so = 51, 10.0, 8
+    rng = np.random.default_rng(3)
+    c = 2000.0 + 300.0 * rng.random((n, n))
+    rho = 1.0 + rng.random((n, n)) if scheme != "const" else None
+    dt = 0.5 * coeffs.critical_dt((h, h), so, c.max())
+    nt = 220
+    prob = oracle.Problem(n=(n, n), h=(h, h), space_order=so, dt=dt, nsteps=nt, scheme=scheme,
+                          nbl=((nbl, nbl), (nbl, nbl)))
+    st = oracle.prepare(prob, c, rho)
+    wav = oracle.ricker(15.0, dt, nt)[:, None]
+    ta = oracle.forward(st, wav, oracle.geometry_table(prob, [a], interp),
+                        oracle.geometry_table(prob, [b], interp), 1).traces[:, 0]
+    tb = oracle.forward(st, wav, oracle.geometry_table(prob, [b], interp),
+                        oracle.geometry_table(prob, [a], interp), 1).traces[:, 0]
+    return ta, tb, rho
+
+
+@pytest.mark.parametrize("interp", ["hicks", "linear"])
+def test_reciprocity_constant_density(interp):
+    ta, tb, _ = _pair_traces("const", (123.4, 171.7), (352.9, 288.1), interp)
+    assert np.linalg.norm(ta - tb) < 1e-12 * np.linalg.norm(ta)
+
+
+def test_reciprocity_staggered_density_ratio():
+    a, b = (120.0, 170.0), (350.0, 290.0)
+    ta, tb, rho = _pair_traces("vd_staggered", a, b, "hicks")
+    ra, rb = rho[12, 17], rho[35, 29]
+    assert np.linalg.norm(ta * ra - tb * rb) < 1e-12 * np.linalg.norm(ta * ra)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_mirror_symmetry_bitwise(ndim):
+    n = 31 if ndim == 2 else 21
+    h, so, c = 10.0, 8, 1500.0
+    dt = 0.5 * coeffs.critical_dt((h,) * ndim, so, c)
+    prob = oracle.Problem(n=(n,) * ndim, h=(h,) * ndim, space_order=so, dt=dt, nsteps=60,
+                          nbl=((6, 6),) * ndim)
+    st = oracle.prepare(prob, np.full((n,) * ndim, c))
+    centre = ((n - 1) * h / 2,) * ndim
+    fw = oracle.forward(st, oracle.ricker(25.0, dt, 60)[:, None],
+                        oracle.geometry_table(prob, [centre]), oracle.geometry_table(prob, []), 0)
+    for ax in range(ndim):
+        assert np.array_equal(fw.p, np.flip(fw.p, axis=ax))
+    assert np.max(np.abs(fw.p)) > 0
+
+
+@pytest.mark.parametrize("scheme", ["vd_staggered", "vd_centred"])
+def test_density_scale_invariance(scheme):
+    n, h, so = 41, 10.0, 4
+    rng = np.random.default_rng(5)
+    c = 2000.0 + 200.0 * rng.random((n, n))
+    rho = 1.0 + rng.random((n, n))
+    dt = 0.5 * coeffs.critical_dt((h, h), so, c.max())
+    prob = oracle.Problem(n=(n, n), h=(h, h), space_order=so, dt=dt, nsteps=120, scheme=scheme,
+                          nbl=((5, 5), (5, 5)))
+    out = []
+    for scale in (1.0, 1000.0):
+        st = oracle.prepare(prob, c, rho * scale)
+        out.append(oracle.forward(st, oracle.ricker(15.0, dt, 120)[:, None],
+                                  oracle.geometry_table(prob, [(200.0, 200.0)]),
+                                  oracle.geometry_table(prob, [(100.0, 300.0)]), 1).traces)
+    assert np.linalg.norm(out[0] - out[1]) < 1e-12 * np.linalg.norm(out[0])
+
+
+def test_absorbing_layer_suppresses_boundary_reflection():
+    n, h, so, c = 61, 10.0, 8, 2000.0
+    dt = 0.5 * coeffs.critical_dt((h, h), so, c)
+    nt = int(0.45 / dt)
+    late = []
+    for nbl in (0, 40):
+        prob = oracle.Problem(n=(n, n), h=(h, h), space_order=so, dt=dt, nsteps=nt,
+                              nbl=((nbl, nbl), (nbl, nbl)))
+        st = oracle.prepare(prob, np.full((n, n), c))
+        tr = oracle.forward(st, oracle.ricker(15.0, dt, nt)[:, None],
+                            oracle.geometry_table(prob, [(300.0, 300.0)]),
+                            oracle.geometry_table(prob, [(300.0, 350.0)]), 1).traces[:, 0]
+        t = (np.arange(nt) + 1) * dt
+        late.append(np.max(np.abs(tr[t > 0.3])))    # after the direct wave has passed
+    assert late[1] < 0.2 * late[0]
