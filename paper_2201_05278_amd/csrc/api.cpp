@@ -1,0 +1,574 @@
+// C ABI of the propagator (declarations and contracts in include/simwave_hip.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "plan.h"
+
+namespace sw {
+const std::string &last_error();
+hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);
+hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
+}  // namespace sw
+
+using namespace sw;
+
+#define SW_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(SW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+namespace {
+
+Geom make_geom(const sw_plan *p)
+{
+    Geom g{};
+    g.Z = p->dims[0];
+    g.X = p->dims[1];
+    g.Y = p->dims[2];
+    g.px = p->pad[1];
+    g.py = p->pad[2];
+    g.origin = p->origin;
+    for (int i = 0; i < 3; ++i) {
+        g.lo[i] = p->lo[i];
+        g.np[i] = p->nphys[i];
+    }
+    return g;
+}
+
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap::Pts &o, void *ws)
+{
+    PointTableDev t{};
+    t.ptr = at<int32_t>(ws, o.ptr);
+    t.node = at<int64_t>(ws, o.node);
+    t.pid = at<int32_t>(ws, o.pid);
+    t.d2 = at<int32_t>(ws, o.d2);
+    t.phys = at<int64_t>(ws, o.phys);
+    t.weight = at<float>(ws, o.weight);
+    t.unode = at<int64_t>(ws, o.unode);
+    t.uptr = at<int32_t>(ws, o.uptr);
+    t.uent = at<int32_t>(ws, o.uent);
+    t.coef_a = at<float>(ws, o.coef_a);
+    t.coef_s = at<float>(ws, o.coef_s);
+    t.wscaled = at<float>(ws, o.wscaled);
+    t.count = ps.count;
+    t.nent = int(ps.node.size());
+    t.nuniq = int(ps.unode.size());
+    t.max_per_point = ps.max_per_point;
+    t.max_per_node = ps.max_per_node;
+    (void)p;
+    return t;
+}
+
+Tiling choose_tiling(const sw_plan *p)
+{
+    Tiling t{};
+    if (p->ndim == 2) {
+        t.tx = 1;
+        t.nw = 1;
+    } else {
+        t.tx = (p->r <= 4) ? 16 : 8;
+        t.nw = 4;
+    }
+    // z chunks: enough blocks to fill 256 CUs several times over
+    const int ntx = (p->dims[1] + t.tx - 1) / t.tx;
+    const int nty = (p->dims[2] + 63) / 64;
+    const int64_t tiles = int64_t(ntx) * nty;
+    const int64_t want = (p->ndim == 2) ? 1024 : 2560;
+    int nzc = int(std::max<int64_t>(1, (want + tiles - 1) / tiles));
+    int zc = (p->dims[0] + nzc - 1) / nzc;
+    zc = std::max(zc, std::min(p->dims[0], 4 * p->r));
+    t.zc = zc;
+    return t;
+}
+
+void fill_params(const sw_plan *p, void *ws, StencilParams &P)
+{
+    std::memset(&P, 0, sizeof(P));
+    P.g = make_geom(p);
+    P.K = at<float>(ws, p->ws.model_k);
+    P.aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
+    P.damp = at<float2>(ws, p->ws.damp);
+    double c0 = 0.0;
+    const double h2z = p->hh[0] * p->hh[0], h2x = p->hh[1] * p->hh[1], h2y = p->hh[2] * p->hh[2];
+    c0 += p->v2[0] / h2z + p->v2[0] / h2y;
+    if (p->ndim == 3) c0 += p->v2[0] / h2x;
+    P.c0 = float(c0);
+    for (int j = 1; j <= p->r; ++j) {
+        P.cz[j] = float(p->v2[j] / h2z);
+        P.cx[j] = (p->ndim == 3) ? float(p->v2[j] / h2x) : 0.0f;
+        P.cy[j] = float(p->v2[j] / h2y);
+        const bool stag = p->prob.scheme == SW_VD_STAGGERED;
+        const double *d = stag ? p->sg : p->w1;
+        P.sz[j] = float(d[j] / p->hh[0]);
+        P.sx[j] = (p->ndim == 3) ? float(d[j] / p->hh[1]) : 0.0f;
+        P.sy[j] = float(d[j] / p->hh[2]);
+        P.mj[j] = float(p->mp[j]);
+    }
+}
+
+void set_tiles(const sw_plan *p, const Tiling &t, StencilParams &P)
+{
+    P.ntx = (p->dims[1] + t.tx - 1) / t.tx;
+    P.nty = (p->dims[2] + 63) / 64;
+    P.zc = t.zc;
+    P.nzc = (p->dims[0] + t.zc - 1) / t.zc;
+}
+
+hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s)
+{
+    const Tiling t = choose_tiling(p);
+    set_tiles(p, t, P);
+    if (p->prob.scheme == SW_CONST) return launch_const(p->r, p->ndim, mode, t, P, s);
+    return launch_vd(p->prob.scheme, p->r, p->ndim, t, P, s);
+}
+
+sw_status check_problem(const sw_problem *q)
+{
+    if (!q) return fail(SW_ERR_ARG, "problem is NULL");
+    if (q->ndim != 2 && q->ndim != 3) return fail(SW_ERR_UNSUPPORTED, "ndim must be 2 or 3");
+    if (q->space_order < 2 || q->space_order > 16 || q->space_order % 2)
+        return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..16");
+    if (q->scheme != SW_CONST && q->scheme != SW_VD_STAGGERED && q->scheme != SW_VD_CENTRED)
+        return fail(SW_ERR_ARG, "unknown scheme");
+    const int r = q->space_order / 2;
+    for (int i = 0; i < q->ndim; ++i) {
+        if (q->n[i] < 1) return fail(SW_ERR_ARG, "grid extents must be >= 1");
+        if (!(q->h[i] > 0.0) || !std::isfinite(q->h[i]))
+            return fail(SW_ERR_ARG, "grid spacing must be positive");
+        for (int s = 0; s < 2; ++s) {
+            if (q->nbl[i][s] < 0) return fail(SW_ERR_ARG, "layer widths must be >= 0");
+            if (q->bc[i][s] != SW_BC_NONE)
+                return fail(SW_ERR_UNSUPPORTED,
+                            "mirror ghost conditions are not provided by this library");
+        }
+        if (int64_t(q->n[i]) + q->nbl[i][0] + q->nbl[i][1] > (1 << 20))
+            return fail(SW_ERR_ARG, "grid extent too large");
+    }
+    if (!(q->dt > 0.0) || !std::isfinite(q->dt)) return fail(SW_ERR_ARG, "dt must be positive");
+    if (q->nsteps < 0) return fail(SW_ERR_ARG, "nsteps must be >= 0");
+    if (!(q->damp_alpha >= 0.0) || !(q->damp_power >= 0.0))
+        return fail(SW_ERR_ARG, "damping parameters must be >= 0");
+    (void)r;
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sw_abi_version(void) { return SW_ABI_VERSION; }
+
+const char *sw_status_str(sw_status s)
+{
+    switch (s) {
+    case SW_OK: return "SW_OK";
+    case SW_ERR_ARG: return "SW_ERR_ARG";
+    case SW_ERR_UNSUPPORTED: return "SW_ERR_UNSUPPORTED";
+    case SW_ERR_DOMAIN: return "SW_ERR_DOMAIN";
+    case SW_ERR_CFL: return "SW_ERR_CFL";
+    case SW_ERR_STATE: return "SW_ERR_STATE";
+    case SW_ERR_WORKSPACE: return "SW_ERR_WORKSPACE";
+    case SW_ERR_HIP: return "SW_ERR_HIP";
+    case SW_ERR_NONFINITE: return "SW_ERR_NONFINITE";
+    }
+    return "SW_ERR_UNKNOWN";
+}
+
+const char *sw_last_error(void) { return sw::last_error().c_str(); }
+
+sw_status sw_critical_dt(int32_t ndim, const double *h, int32_t space_order, double cmax, double *dt)
+{
+    set_error("");
+    if ((ndim != 2 && ndim != 3) || !h || !dt) return fail(SW_ERR_ARG, "bad arguments");
+    if (space_order < 2 || space_order > 16 || space_order % 2)
+        return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..16");
+    if (!(cmax > 0.0)) return fail(SW_ERR_ARG, "cmax must be positive");
+    const double a = a1d(space_order);
+    double s = 0.0;
+    for (int i = 0; i < ndim; ++i) {
+        if (!(h[i] > 0.0)) return fail(SW_ERR_ARG, "spacing must be positive");
+        s += a / (h[i] * h[i]);
+    }
+    *dt = 2.0 / (cmax * std::sqrt(s));
+    return SW_OK;
+}
+
+sw_status sw_steps_for(double tf, double dt, int32_t *n)
+{
+    set_error("");
+    if (!n || !(dt > 0.0) || !(tf >= 0.0)) return fail(SW_ERR_ARG, "bad arguments");
+    const double k = std::ceil(tf / dt) + 1.0;
+    if (k > 2.0e9) return fail(SW_ERR_ARG, "too many steps");
+    *n = int32_t(k);
+    return SW_OK;
+}
+
+sw_status sw_ricker(double f, double t0, double dt, int32_t n, float *out)
+{
+    set_error("");
+    if (!(f > 0.0) || !(dt > 0.0) || n < 0 || (n > 0 && !out)) return fail(SW_ERR_ARG, "bad arguments");
+    if (t0 <= 0.0) t0 = 1.0 / f;
+    for (int32_t k = 0; k < n; ++k) {
+        const double t = k * dt - t0;
+        const double a = M_PI * M_PI * f * f * t * t;
+        out[k] = float((1.0 - 2.0 * a) * std::exp(-a));
+    }
+    return SW_OK;
+}
+
+sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
+{
+    set_error("");
+    if (!out) return fail(SW_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    sw_status st = check_problem(prob);
+    if (st != SW_OK) return st;
+    sw_plan *p = new (std::nothrow) sw_plan();
+    if (!p) return fail(SW_ERR_ARG, "out of host memory");
+    p->prob = *prob;
+    if (p->prob.ndim == 2) {
+        p->prob.n[2] = 1;
+        p->prob.h[2] = 1.0;
+        p->prob.nbl[2][0] = p->prob.nbl[2][1] = 0;
+    }
+    build_layout(p);
+    *out = p;
+    return SW_OK;
+}
+
+sw_status sw_plan_destroy(sw_plan *plan)
+{
+    set_error("");
+    if (!plan) return SW_OK;
+    if (plan->graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(plan->graph_exec));
+    if (plan->capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(plan->capture_stream));
+    delete plan;
+    return SW_OK;
+}
+
+sw_status sw_plan_layout(const sw_plan *p, sw_layout *out)
+{
+    set_error("");
+    if (!p || !out) return fail(SW_ERR_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->ndim = p->ndim;
+    if (p->ndim == 3) {
+        for (int i = 0; i < 3; ++i) out->dims[i] = p->dims[i];
+        out->padded[0] = p->pad[0];
+        out->padded[1] = p->pad[1];
+        out->padded[2] = p->pad[2];
+    } else {
+        out->dims[0] = p->dims[0];
+        out->dims[1] = p->dims[2];
+        out->dims[2] = 1;
+        out->padded[0] = p->pad[0];
+        out->padded[1] = p->pad[2];
+        out->padded[2] = 1;
+    }
+    out->halo = p->halo;
+    out->origin = p->origin;
+    out->field_elems = p->field_elems;
+    out->grid_nodes = p->grid_nodes;
+    out->physical_nodes = p->phys_nodes;
+    out->nsrc = p->src.count;
+    out->nrec = p->rec.count;
+    out->workspace_bytes = int64_t(p->ws.total);
+    return SW_OK;
+}
+
+sw_status sw_plan_set_geometry(sw_plan *p, int32_t which, int32_t count, const double *coords,
+                               int32_t interp, int32_t radius, double kaiser_b)
+{
+    set_error("");
+    if (!p) return fail(SW_ERR_ARG, "plan is NULL");
+    if (which != SW_SRC && which != SW_REC) return fail(SW_ERR_ARG, "which must be SW_SRC or SW_REC");
+    sw_status st = build_points(p, which == SW_SRC ? p->src : p->rec, count, coords, interp, radius,
+                                kaiser_b);
+    if (st != SW_OK) return st;
+    p->prepared = false;
+    return SW_OK;
+}
+
+sw_status sw_plan_points(const sw_plan *p, int32_t which, int64_t *nent, int64_t *nodes,
+                         int32_t *ids, float *weights)
+{
+    set_error("");
+    if (!p || !nent) return fail(SW_ERR_ARG, "NULL argument");
+    if (which != SW_SRC && which != SW_REC) return fail(SW_ERR_ARG, "which must be SW_SRC or SW_REC");
+    const PointSet &ps = which == SW_SRC ? p->src : p->rec;
+    const int64_t n = int64_t(ps.node.size());
+    if (nodes || ids || weights) {
+        if (*nent < n) return fail(SW_ERR_ARG, "arrays too small");
+        for (int64_t e = 0; e < n; ++e) {
+            if (nodes) nodes[e] = ps.node[e];
+            if (ids) ids[e] = ps.pid[e];
+            if (weights) weights[e] = ps.weight[e];
+        }
+    }
+    *nent = n;
+    return SW_OK;
+}
+
+static sw_status upload_points(sw_plan *p, const PointSet &ps, const WorkspaceMap::Pts &o, void *ws,
+                               hipStream_t s)
+{
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(static_cast<char *>(ws) + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    SW_HIP(up(o.ptr, ps.ptr.data(), ps.ptr.size() * sizeof(int32_t)));
+    SW_HIP(up(o.node, ps.node.data(), ps.node.size() * sizeof(int64_t)));
+    SW_HIP(up(o.pid, ps.pid.data(), ps.pid.size() * sizeof(int32_t)));
+    SW_HIP(up(o.d2, ps.d2.data(), ps.d2.size() * sizeof(int32_t)));
+    SW_HIP(up(o.phys, ps.phys.data(), ps.phys.size() * sizeof(int64_t)));
+    SW_HIP(up(o.weight, ps.weight.data(), ps.weight.size() * sizeof(float)));
+    SW_HIP(up(o.unode, ps.unode.data(), ps.unode.size() * sizeof(int64_t)));
+    SW_HIP(up(o.uptr, ps.uptr.data(), ps.uptr.size() * sizeof(int32_t)));
+    SW_HIP(up(o.uent, ps.uent.data(), ps.uent.size() * sizeof(int32_t)));
+    (void)p;
+    return SW_OK;
+}
+
+sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, double cmax, void *ws,
+                           void *stream)
+{
+    set_error("");
+    if (!p || !vel || !ws) return fail(SW_ERR_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SW_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (p->prob.scheme != SW_CONST && !rho) return fail(SW_ERR_ARG, "variable density needs rho");
+    if (!(cmax > 0.0)) return fail(SW_ERR_ARG, "cmax must be positive");
+    double dtc = 0.0;
+    sw_status st = sw_critical_dt(p->ndim, p->ndim == 3 ? p->prob.h : p->prob.h, p->prob.space_order,
+                                  cmax, &dtc);
+    if (st != SW_OK) return st;
+    if (p->prob.dt > dtc * (1.0 + 1e-12))
+        return fail(SW_ERR_CFL, "dt " + std::to_string(p->prob.dt) + " exceeds the stability limit " +
+                                    std::to_string(dtc));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geom g = make_geom(p);
+    float *K = at<float>(ws, p->ws.model_k);
+    float *aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
+    SW_HIP(launch_model_prep(g, p->hz, p->hx, p->pad[0], p->prob.scheme, p->prob.dt, vel, rho, K, aux, s));
+    SW_HIP(hipMemcpyAsync(at<char>(ws, p->ws.damp), p->damp.data(), p->damp.size() * sizeof(float),
+                          hipMemcpyHostToDevice, s));
+    st = upload_points(p, p->src, p->ws.src, ws, s);
+    if (st != SW_OK) return st;
+    st = upload_points(p, p->rec, p->ws.rec, ws, s);
+    if (st != SW_OK) return st;
+    const float2 *damp = at<float2>(ws, p->ws.damp);
+    SW_HIP(launch_point_coef(table_dev(p, p->src, p->ws.src, ws), damp, vel, p->prob.dt, 1.0 / p->dV, s));
+    SW_HIP(launch_point_coef(table_dev(p, p->rec, p->ws.rec, ws), damp, vel, p->prob.dt, 1.0, s));
+    p->prepared = true;
+    p->prepared_ws = ws;
+    return SW_OK;
+}
+
+static sw_status check_prepared(const sw_plan *p, void *ws)
+{
+    if (!p->prepared) return fail(SW_ERR_STATE, "sw_model_prepare must run after the last geometry change");
+    if (ws != p->prepared_ws) return fail(SW_ERR_WORKSPACE, "workspace differs from the prepared one");
+    return SW_OK;
+}
+
+// Enqueue the forward steps of io on s.
+static sw_status enqueue_forward(sw_plan *p, const sw_fwd_io *io, hipStream_t s)
+{
+    void *ws = io->workspace;
+    StencilParams P;
+    fill_params(p, ws, P);
+    const PointTableDev src = table_dev(p, p->src, p->ws.src, ws);
+    const PointTableDev rec = table_dev(p, p->rec, p->ws.rec, ws);
+    const Geom g = make_geom(p);
+    if (io->step0 == 0) {
+        SW_HIP(launch_fill(io->field[0], p->field_elems, 0.0f, s));
+        SW_HIP(launch_fill(io->field[1], p->field_elems, 0.0f, s));
+    }
+    std::vector<hipEvent_t> ev;
+    if (io->stencil_ms) {
+        ev.resize(2 * size_t(io->nsteps_run));
+        for (auto &e : ev) SW_HIP(hipEventCreate(&e));
+    }
+    auto release = [&]() {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    };
+    for (int k = 0; k < io->nsteps_run; ++k) {
+        const int n = io->step0 + k;
+        float *cur = io->field[k % 2];
+        float *nxt = io->field[(k + 1) % 2];
+        if (io->ckpt && n % io->ckpt_every == 0) {
+            float *slot = io->ckpt + size_t(n / io->ckpt_every) * 2 * p->field_elems;
+            SW_HIP(launch_copy(slot, cur, p->field_elems, s));
+            SW_HIP(launch_copy(slot + p->field_elems, nxt, p->field_elems, s));
+        }
+        P.cur = cur;
+        P.nxt = nxt;
+        if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * k], s));
+        SW_HIP(stencil(p, MODE_FWD, P, s));
+        if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * k + 1], s));
+        if (src.count) SW_HIP(launch_inject(src, nxt, nullptr, io->wavelet + size_t(n) * src.count, s));
+        if (rec.count) SW_HIP(launch_record(rec, nxt, io->traces + size_t(n) * rec.count, s));
+        if (io->snaps && io->saving_stride > 0 && (n + 1) % io->saving_stride == 0)
+            SW_HIP(launch_snapshot(g, nxt, io->snaps + size_t((n + 1) / io->saving_stride - 1) * p->grid_nodes, s));
+    }
+    if (!ev.empty()) {
+        const hipError_t e = hipEventSynchronize(ev.back());
+        if (e != hipSuccess) {
+            release();
+            return fail(SW_ERR_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        }
+        for (int k = 0; k < io->nsteps_run; ++k) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+            io->stencil_ms[k] = ms;
+        }
+    }
+    release();
+    return SW_OK;
+}
+
+sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
+{
+    set_error("");
+    if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
+    sw_status st = check_prepared(p, io->workspace);
+    if (st != SW_OK) return st;
+    if (!io->field[0] || !io->field[1] || io->field[0] == io->field[1])
+        return fail(SW_ERR_ARG, "two distinct wavefield buffers are required");
+    if (io->step0 < 0 || io->nsteps_run < 0 || int64_t(io->step0) + io->nsteps_run > p->prob.nsteps)
+        return fail(SW_ERR_ARG, "step range outside [0, nsteps]");
+    if (p->src.count && !io->wavelet) return fail(SW_ERR_ARG, "wavelet is NULL");
+    if (p->rec.count && !io->traces) return fail(SW_ERR_ARG, "traces is NULL");
+    if (io->ckpt && io->ckpt_every <= 0) return fail(SW_ERR_ARG, "ckpt_every must be > 0");
+    if (io->snaps && io->saving_stride < 0) return fail(SW_ERR_ARG, "saving_stride must be >= 0");
+    if (io->stencil_ms && io->use_graph) return fail(SW_ERR_ARG, "stencil timing is not available with graphs");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!io->use_graph) return enqueue_forward(p, io, s);
+
+    // Capture the whole loop once, on a private stream (the legacy default
+    // stream cannot be captured), and replay the graph on the caller's stream
+    // whenever the same run is asked again.
+    const std::vector<uint64_t> key = {
+        uint64_t(uintptr_t(io->workspace)), uint64_t(uintptr_t(io->wavelet)),
+        uint64_t(uintptr_t(io->field[0])), uint64_t(uintptr_t(io->field[1])),
+        uint64_t(uintptr_t(io->traces)), uint64_t(uintptr_t(io->snaps)), uint64_t(io->saving_stride),
+        uint64_t(uintptr_t(io->ckpt)), uint64_t(io->ckpt_every), uint64_t(io->step0),
+        uint64_t(io->nsteps_run)};
+    if (!p->graph_exec || p->graph_key != key) {
+        if (p->graph_exec) {
+            (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
+            p->graph_exec = nullptr;
+        }
+        if (!p->capture_stream) {
+            hipStream_t cs = nullptr;
+            SW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            p->capture_stream = cs;
+        }
+        hipStream_t cs = static_cast<hipStream_t>(p->capture_stream);
+        SW_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        st = enqueue_forward(p, io, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (st != SW_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(SW_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        p->graph_exec = exec;
+        p->graph_key = key;
+    }
+    SW_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(p->graph_exec), s));
+    return SW_OK;
+}
+
+sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
+{
+    set_error("");
+    if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
+    sw_status st = check_prepared(p, io->workspace);
+    if (st != SW_OK) return st;
+    if (p->prob.scheme != SW_CONST)
+        return fail(SW_ERR_UNSUPPORTED, "the adjoint covers the constant-density scheme");
+    if (!io->residual || !io->ckpt || io->ckpt_every <= 0 || !io->field[0] || !io->field[1] ||
+        !io->adj[0] || !io->adj[1] || !io->segment || !io->grad_m || !io->grad_vel || !io->vel)
+        return fail(SW_ERR_ARG, "missing buffer");
+    if (p->src.count && !io->wavelet) return fail(SW_ERR_ARG, "wavelet is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = io->workspace;
+    const int64_t fe = p->field_elems;
+    const int N = p->prob.nsteps;
+    const int E = io->ckpt_every;
+    const PointTableDev src = table_dev(p, p->src, p->ws.src, ws);
+    const PointTableDev rec = table_dev(p, p->rec, p->ws.rec, ws);
+    StencilParams P;
+    fill_params(p, ws, P);
+    SW_HIP(launch_fill(io->grad_m, fe, 0.0f, s));
+    SW_HIP(launch_fill(io->adj[0], fe, 0.0f, s));
+    SW_HIP(launch_fill(io->adj[1], fe, 0.0f, s));
+    float *acur = io->adj[0];   // phi^{m+1}
+    float *anxt = io->adj[1];   // phi^{m+2}, overwritten by phi^m
+    const int nseg = (N + E - 1) / E;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int k = seg * E;
+        const int L = std::min(E, N - k);
+        // restore (u^k, u^{k-1}) and recompute u^{k+1..k+L}, storing M (L u^n + Q s^n)
+        const float *slot = io->ckpt + size_t(seg) * 2 * fe;
+        SW_HIP(launch_copy(io->field[0], slot, fe, s));
+        SW_HIP(launch_copy(io->field[1], slot + fe, fe, s));
+        for (int i = 0; i < L; ++i) {
+            const int n = k + i;
+            float *cur = io->field[i % 2];
+            float *nxt = io->field[(i + 1) % 2];
+            float *lvl = io->segment + size_t(i) * fe;
+            P.cur = cur;
+            P.nxt = nxt;
+            P.store = lvl;
+            P.grad = nullptr;
+            SW_HIP(stencil(p, MODE_STORE, P, s));
+            if (src.count) SW_HIP(launch_inject(src, nxt, lvl, io->wavelet + size_t(n) * src.count, s));
+        }
+        // adjoint steps m = top .. k (top = N in the last segment)
+        const int top = (seg == nseg - 1) ? N : k + L - 1;
+        for (int m = top; m >= k; --m) {
+            P.cur = acur;
+            P.nxt = anxt;
+            if (m <= N - 1) {
+                P.store = io->segment + size_t(m - k) * fe;
+                P.grad = io->grad_m;
+                SW_HIP(stencil(p, MODE_IMAGE, P, s));
+            } else {
+                P.store = nullptr;
+                P.grad = nullptr;
+                SW_HIP(stencil(p, MODE_FWD, P, s));
+            }
+            if (m >= 1) {
+                if (rec.count) SW_HIP(launch_inject(rec, anxt, nullptr, io->residual + size_t(m - 1) * rec.count, s));
+                if (io->src_adjoint && src.count)
+                    SW_HIP(launch_record(src, anxt, io->src_adjoint + size_t(m - 1) * src.count, s));
+            }
+            std::swap(acur, anxt);   // phi^m becomes the current level
+        }
+    }
+    SW_HIP(launch_fold_gradient(make_geom(p), io->grad_m, io->vel, p->prob.dt, io->grad_vel, s));
+    return SW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Kernel parameter blocks and launcher declarations shared by the HIP
+// translation units and the C ABI layer.
+#pragma once
+
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace sw {
+
+// Extended grid in the internal (z, x, y) view plus its padded layout.
+struct Geom {
+    int Z, X, Y;            // extended grid extents
+    int px, py;             // padded x extent and row pitch
+    int64_t origin;         // element offset of node (0, 0, 0)
+    int lo[3];              // layer width on the low side (physical box start)
+    int np[3];              // physical extents
+};
+
+__host__ __device__ inline int64_t elem(const Geom &g, int z, int x, int y)
+{
+    return g.origin + (int64_t(z) * g.px + x) * g.py + y;
+}
+
+enum StencilMode { MODE_FWD = 0, MODE_STORE = 1, MODE_IMAGE = 2 };
+
+struct StencilParams {
+    float *nxt;             // p^{n-1} on entry, p^{n+1} on exit (in place)
+    const float *cur;       // p^n
+    const float *K;         // multiplier of (L p): dt^2 c^2, or dt^2 rho c^2
+    const float *aux;       // b = 1/rho (staggered) or rho (centred); unused otherwise
+    const float2 *damp;     // (A, B) by squared layer distance
+    float *store;           // MODE_STORE: K (L p) written; MODE_IMAGE: read
+    float *grad;            // MODE_IMAGE: += p * store / K^2
+    Geom g;
+    float c0;               // sum over axes of v_0 / h^2
+    float cz[9], cx[9], cy[9];     // second-derivative v_j / h^2 per axis
+    float sz[9], sx[9], sy[9];     // staggered s_j / h, or centred c_j / h (first derivative)
+    float mj[9];            // midpoint interpolation weights
+    int ntx, nty, nzc, zc;  // tiling: tiles along x, y; z chunks and chunk length
+};
+
+// Tiling chosen by the host for one stencil launch.
+struct Tiling {
+    int tx;                 // rows (x) per tile
+    int nw;                 // waves per block
+    int zc;                 // z-chunk length
+};
+
+hipError_t launch_stencil(int scheme, int r, int ndim, int mode, const Tiling &t,
+                          StencilParams &P, hipStream_t s);
+
+// ---- point and utility kernels ----
+struct PointTableDev {
+    const int32_t *ptr;     // by point: entries ptr[k] .. ptr[k+1]
+    const int64_t *node;
+    const int32_t *pid;
+    const int32_t *d2;
+    const int64_t *phys;
+    const float *weight;
+    const int64_t *unode;   // by unique node
+    const int32_t *uptr;
+    const int32_t *uent;
+    float *coef_a;
+    float *coef_s;
+    float *wscaled;
+    int count, nent, nuniq, max_per_point, max_per_node;
+};
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int scheme,
+                             double dt, const float *vel, const float *rho, float *K, float *aux,
+                             hipStream_t s);
+hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel,
+                             double dt, double inv_dv, hipStream_t s);
+hipError_t launch_inject(const PointTableDev &t, float *field, float *store, const float *amp,
+                         hipStream_t s);
+hipError_t launch_record(const PointTableDev &t, const float *field, float *out, hipStream_t s);
+hipError_t launch_snapshot(const Geom &g, const float *field, float *out, hipStream_t s);
+hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float *vel, double dt,
+                                float *grad_vel, hipStream_t s);
+
+}  // namespace sw

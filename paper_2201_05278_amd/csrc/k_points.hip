@@ -1,0 +1,272 @@
+// Point kernels (source injection, receiver recording) and small utility
+// kernels (buffer fill/copy, model preparation, snapshots, gradient fold).
+//
+// Injection is a gather over unique grid nodes: each node sums its table
+// entries in a fixed order and adds the sum once, so results are deterministic
+// and no atomics are needed.  Recording sums each receiver's entries.  Both
+// give a group of G lanes (a power of two up to the wavefront width) to one
+// node or receiver and finish with a butterfly reduction inside the group.
+#include "device.h"
+
+namespace sw {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_fill(float *__restrict__ p, int64_t n, float v)
+{
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64_t n)
+{
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        d[i] = s[i];
+}
+
+// Every element of the padded arrays receives the model value of the nearest
+// physical node (edge replication into the layer, the halo and the row slack).
+__global__ void k_model_prep(Geom g, int hz, int hx, int pz, int scheme, float dt2,
+                             const float *__restrict__ vel, const float *__restrict__ rho,
+                             float *__restrict__ K, float *__restrict__ aux)
+{
+    const int64_t total = int64_t(pz) * g.px * g.py;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int yy = int(i % g.py);
+        const int64_t t = i / g.py;
+        const int xx = int(t % g.px);
+        const int zz = int(t / g.px);
+        const int z = zz - hz, x = xx - hx, y = yy - 64;
+        const int pzc = min(max(z - g.lo[0], 0), g.np[0] - 1);
+        const int pxc = min(max(x - g.lo[1], 0), g.np[1] - 1);
+        const int pyc = min(max(y - g.lo[2], 0), g.np[2] - 1);
+        const int64_t ph = (int64_t(pzc) * g.np[1] + pxc) * g.np[2] + pyc;
+        const float c = vel[ph];
+        const float m = dt2 * c * c;
+        if (scheme == 0) {
+            K[i] = m;
+        } else if (scheme == 1) {   // staggered: K = dt^2 rho c^2, aux = 1/rho
+            const float r = rho[ph];
+            K[i] = m * r;
+            aux[i] = 1.0f / r;
+        } else {                    // centred: K = dt^2 c^2, aux = rho
+            K[i] = m;
+            aux[i] = rho[ph];
+        }
+    }
+}
+
+// Per entry: A(node) dt^2 c(node)^2 w s (injection), dt^2 c^2 w s (the source
+// part of the stored M (L u + Q s) levels) and w s (recording), with s = 1/dV
+// for sources and 1 for receivers.
+__global__ void k_point_coef(PointTableDev t, const float2 *__restrict__ damp,
+                             const float *__restrict__ vel, double dt, double scale)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= t.nent) return;
+    const double c = vel[t.phys[e]];
+    const double m = dt * dt * c * c;
+    const double a = damp[t.d2[e]].x;
+    const double w = double(t.weight[e]) * scale;
+    t.coef_a[e] = float(a * m * w);
+    t.coef_s[e] = float(m * w);
+    t.wscaled[e] = float(w);
+}
+
+template <int G>
+__device__ inline float group_sum(float v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_inject(PointTableDev t, float *__restrict__ field,
+                                                   float *__restrict__ store,
+                                                   const float *__restrict__ amp)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = gid / G, sub = gid % G;
+    float sa = 0.0f, ss = 0.0f;
+    if (u < t.nuniq) {
+        for (int k = t.uptr[u] + sub; k < t.uptr[u + 1]; k += G) {
+            const int e = t.uent[k];
+            const float s = amp[t.pid[e]];
+            sa += t.coef_a[e] * s;
+            ss += t.coef_s[e] * s;
+        }
+    }
+    sa = group_sum<G>(sa);
+    ss = group_sum<G>(ss);
+    if (u < t.nuniq && sub == 0) {
+        const int64_t n = t.unode[u];
+        field[n] += sa;
+        if (store) store[n] += ss;
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_record(PointTableDev t, const float *__restrict__ field,
+                                                   float *__restrict__ out)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pt = gid / G, sub = gid % G;
+    float acc = 0.0f;
+    if (pt < t.count)
+        for (int e = t.ptr[pt] + sub; e < t.ptr[pt + 1]; e += G) acc += t.wscaled[e] * field[t.node[e]];
+    acc = group_sum<G>(acc);
+    if (pt < t.count && sub == 0) out[pt] = acc;
+}
+
+__global__ void k_snapshot(Geom g, const float *__restrict__ f, float *__restrict__ out)
+{
+    const int64_t total = int64_t(g.Z) * g.X * g.Y;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int y = int(i % g.Y);
+        const int64_t t = i / g.Y;
+        const int x = int(t % g.X);
+        const int z = int(t / g.X);
+        out[i] = f[elem(g, z, x, y)];
+    }
+}
+
+// dJ/dc on the physical grid: every extended-grid node copies its model from
+// one physical node, so the physical node gathers 2 dt^2 c dJ/dM over the
+// block of extended nodes that copy it (a single node away from the edges).
+__global__ void k_fold_gradient(Geom g, const float *__restrict__ gm, const float *__restrict__ vel,
+                                float two_dt2, float *__restrict__ gv)
+{
+    const int64_t total = int64_t(g.np[0]) * g.np[1] * g.np[2];
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int py = int(i % g.np[2]);
+        const int64_t t = i / g.np[2];
+        const int px = int(t % g.np[1]);
+        const int pz = int(t / g.np[1]);
+        const int ext[3] = {g.Z, g.X, g.Y};
+        const int pc[3] = {pz, px, py};
+        int a[3], b[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = pc[k] + g.lo[k];
+            b[k] = a[k];
+            if (pc[k] == 0) a[k] = 0;
+            if (pc[k] == g.np[k] - 1) b[k] = ext[k] - 1;
+        }
+        float s = 0.0f;
+        for (int z = a[0]; z <= b[0]; ++z)
+            for (int x = a[1]; x <= b[1]; ++x)
+                for (int y = a[2]; y <= b[2]; ++y) s += gm[elem(g, z, x, y)];
+        gv[i] = s * two_dt2 * vel[i];
+    }
+}
+
+// Grid size for the grid-stride kernels (capped) ...
+int blocks_for(int64_t n, int per = kBlock)
+{
+    int64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return int(b);
+}
+
+// ... and for the one-thread-per-item point kernels (not capped).
+int blocks_exact(int64_t n)
+{
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return int(b < 1 ? 1 : b);
+}
+
+int group_size(int max_entries)
+{
+    int g = 1;
+    while (g < max_entries && g < 64) g <<= 1;
+    return g;
+}
+
+}  // namespace
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int scheme, double dt,
+                             const float *vel, const float *rho, float *K, float *aux,
+                             hipStream_t s)
+{
+    const int64_t total = int64_t(pz) * g.px * g.py;
+    hipLaunchKernelGGL(k_model_prep, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, halo_z,
+                       halo_x, pz, scheme, float(dt * dt), vel, rho, K, aux);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel,
+                             double dt, double scale, hipStream_t s)
+{
+    if (t.nent <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_point_coef, dim3(blocks_for(t.nent)), dim3(kBlock), 0, s, t, damp, vel,
+                       dt, scale);
+    return hipGetLastError();
+}
+
+#define SW_GROUP_DISPATCH(G, KERNEL, N, ...)                                                    \
+    switch (G) {                                                                                \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(blocks_exact(int64_t(N) * 1)), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(blocks_exact(int64_t(N) * 2)), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(blocks_exact(int64_t(N) * 4)), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, dim3(blocks_exact(int64_t(N) * 8)), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, dim3(blocks_exact(int64_t(N) * 16)), dim3(kBlock), 0, __VA_ARGS__); break; \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(blocks_exact(int64_t(N) * 32)), dim3(kBlock), 0, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<64>, dim3(blocks_exact(int64_t(N) * 64)), dim3(kBlock), 0, __VA_ARGS__); break; \
+    }
+
+hipError_t launch_inject(const PointTableDev &t, float *field, float *store, const float *amp,
+                         hipStream_t s)
+{
+    if (t.nuniq <= 0) return hipSuccess;
+    const int G = group_size(t.max_per_node);
+    SW_GROUP_DISPATCH(G, k_inject, t.nuniq, s, t, field, store, amp);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(const PointTableDev &t, const float *field, float *out, hipStream_t s)
+{
+    if (t.count <= 0) return hipSuccess;
+    const int G = group_size(t.max_per_point);
+    SW_GROUP_DISPATCH(G, k_record, t.count, s, t, field, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const Geom &g, const float *field, float *out, hipStream_t s)
+{
+    const int64_t total = int64_t(g.Z) * g.X * g.Y;
+    hipLaunchKernelGGL(k_snapshot, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, field, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float *vel, double dt,
+                                float *grad_vel, hipStream_t s)
+{
+    const int64_t total = int64_t(g.np[0]) * g.np[1] * g.np[2];
+    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, grad_m,
+                       vel, float(2.0 * dt * dt), grad_vel);
+    return hipGetLastError();
+}
+
+}  // namespace sw

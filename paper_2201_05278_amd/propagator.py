@@ -1,0 +1,285 @@
+"""Python front-end over the C ABI: argument marshalling and torch buffers.
+
+Every numerical step runs in the HIP library; this module only allocates
+device buffers with torch, fills the ABI structs and calls the library on the
+current torch stream.
+
+Vocabulary follows the paper ("Example of use"): a physical grid with spacing
+h, a space order, an absorbing layer added on each side, sources and
+receivers at coordinates in metres, a wavelet per source, and forward()
+returning receiver traces and wavefields.
+"""
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _pairs(v, ndim):
+    if isinstance(v, int):
+        return [(v, v)] * ndim
+    return [tuple(int(a) for a in x) for x in v]
+
+
+def critical_dt(h, space_order, cmax):
+    h = list(h)
+    arr = (ctypes.c_double * 3)(*(h + [1.0] * (3 - len(h))))
+    out = ctypes.c_double()
+    L.check("sw_critical_dt", L.lib().sw_critical_dt(len(h), arr, space_order, cmax, ctypes.byref(out)))
+    return out.value
+
+
+def steps_for(tf, dt):
+    out = ctypes.c_int32()
+    L.check("sw_steps_for", L.lib().sw_steps_for(tf, dt, ctypes.byref(out)))
+    return out.value
+
+
+def ricker(f_peak, dt, nsteps, t0=0.0):
+    buf = (ctypes.c_float * max(1, nsteps))()
+    L.check("sw_ricker", L.lib().sw_ricker(f_peak, t0, dt, nsteps, buf))
+    return torch.tensor(list(buf)[:nsteps], dtype=torch.float32)
+
+
+@dataclass
+class ForwardResult:
+    traces: torch.Tensor        # (nsteps, nrec)
+    fields: tuple               # the two wavefield buffers (padded layout)
+    current: int                # index in fields of the last level p^{end}
+    snaps: torch.Tensor = None  # (nsnap, *grid dims)
+    ckpt: torch.Tensor = None   # (nckpt, 2, field_elems)
+    checkpoint_every: int = 0
+
+
+class Propagator:
+    """One plan: grid, scheme, time axis, absorbing layer, geometry, model."""
+
+    def __init__(self, n, h, space_order, dt, nsteps, scheme="const", nbl=0, alpha=0.001,
+                 power=3.0, device="cuda"):
+        ndim = len(n)
+        prob = L.Problem()
+        prob.ndim = ndim
+        for i in range(3):
+            prob.n[i] = int(n[i]) if i < ndim else 1
+            prob.h[i] = float(h[i]) if i < ndim else 1.0
+        prob.space_order = int(space_order)
+        prob.scheme = L.SCHEMES[scheme]
+        for i, (a, b) in enumerate(_pairs(nbl, ndim)):
+            prob.nbl[i][0] = a
+            prob.nbl[i][1] = b
+        prob.damp_alpha = float(alpha)
+        prob.damp_power = float(power)
+        prob.dt = float(dt)
+        prob.nsteps = int(nsteps)
+        self.prob = prob
+        self.ndim = ndim
+        self.n = tuple(int(x) for x in n)
+        self.scheme = scheme
+        self.nsteps = int(nsteps)
+        self.dt = float(dt)
+        self.device = torch.device(device)
+        handle = ctypes.c_void_p()
+        L.check("sw_plan_create", L.lib().sw_plan_create(ctypes.byref(prob), ctypes.byref(handle)))
+        self._plan = handle
+        self.workspace = None
+        self._vel = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None):
+                L.lib().sw_plan_destroy(self._plan)
+                self._plan = None
+        except Exception:
+            pass
+
+    # ---- layout -----------------------------------------------------------
+    @property
+    def layout(self):
+        lay = L.Layout()
+        L.check("sw_plan_layout", L.lib().sw_plan_layout(self._plan, ctypes.byref(lay)))
+        return lay
+
+    @property
+    def grid_shape(self):
+        lay = self.layout
+        return tuple(lay.dims[:self.ndim])
+
+    def new_field(self):
+        return torch.zeros(self.layout.field_elems, dtype=torch.float32, device=self.device)
+
+    def grid_view(self, buf):
+        """Extended-grid view of a padded-layout buffer (no copy)."""
+        lay = self.layout
+        if self.ndim == 3:
+            p1, p2 = lay.padded[1], lay.padded[2]
+            return buf.as_strided(tuple(lay.dims[:3]), (p1 * p2, p2, 1), lay.origin)
+        p1 = lay.padded[1]
+        return buf.as_strided(tuple(lay.dims[:2]), (p1, 1), lay.origin)
+
+    def physical_view(self, grid):
+        """Physical part of an extended-grid array (paper: remove_nbl)."""
+        sl = tuple(slice(int(self.prob.nbl[i][0]), int(self.prob.nbl[i][0]) + self.n[i])
+                   for i in range(self.ndim))
+        return grid[sl]
+
+    # ---- geometry and model -------------------------------------------------
+    def _set_points(self, which, coords, interp, radius, kaiser_b):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(-1, self.ndim))
+        arr = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        L.check("sw_plan_set_geometry",
+                L.lib().sw_plan_set_geometry(self._plan, which, c.shape[0], arr, L.INTERPS[interp],
+                                             int(radius), float(kaiser_b or 0.0)))
+
+    def set_sources(self, coords, interp="hicks", radius=4, kaiser_b=None):
+        self._set_points(L.SW_SRC, coords, interp, radius, kaiser_b)
+        self._vel = None
+
+    def set_receivers(self, coords, interp="hicks", radius=4, kaiser_b=None):
+        self._set_points(L.SW_REC, coords, interp, radius, kaiser_b)
+        self._vel = None
+
+    def point_table(self, which):
+        """Host table (nodes, ids, weights) of sources ('src') or receivers ('rec')."""
+        import numpy as np
+        w = L.SW_SRC if which == "src" else L.SW_REC
+        n = ctypes.c_int64(0)
+        L.check("sw_plan_points", L.lib().sw_plan_points(self._plan, w, ctypes.byref(n), None, None, None))
+        nodes = np.zeros(max(1, n.value), np.int64)
+        ids = np.zeros(max(1, n.value), np.int32)
+        wts = np.zeros(max(1, n.value), np.float32)
+        L.check("sw_plan_points", L.lib().sw_plan_points(
+            self._plan, w, ctypes.byref(n), nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            wts.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return nodes[:n.value], ids[:n.value], wts[:n.value]
+
+    def prepare(self, vel, rho=None, cmax=None):
+        """Build the device model arrays from physical-grid velocity (and density)."""
+        vel = vel.to(self.device, torch.float32).contiguous()
+        if rho is not None:
+            rho = rho.to(self.device, torch.float32).contiguous()
+        if tuple(vel.shape) != self.n:
+            raise ValueError(f"velocity shape {tuple(vel.shape)} != grid {self.n}")
+        lay = self.layout
+        nbytes = int(lay.workspace_bytes)
+        if self.workspace is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        cmax = float(vel.max().item()) if cmax is None else float(cmax)
+        L.check("sw_model_prepare", L.lib().sw_model_prepare(
+            self._plan, _ptr(vel), _ptr(rho), cmax, _ptr(self.workspace), _stream()))
+        self._vel = vel
+        self._rho = rho
+        return self
+
+    # ---- propagation --------------------------------------------------------
+    def forward(self, wavelet, saving_stride=0, checkpoint_every=0, use_graph=False, fields=None,
+                step0=0, nsteps_run=None, traces=None, stencil_ms=None):
+        """Run steps step0 .. step0+nsteps_run-1 (all by default).  stencil_ms: a
+        host float32 numpy array of nsteps_run entries to receive each stencil
+        launch's duration (the call then waits for the GPU)."""
+        if self._vel is None:
+            raise RuntimeError("prepare() must be called after the geometry is set")
+        lay = self.layout
+        nrun = self.nsteps - step0 if nsteps_run is None else int(nsteps_run)
+        if fields is None:
+            fields = (self.new_field(), self.new_field())
+        if lay.nsrc:
+            wavelet = wavelet.to(self.device, torch.float32).reshape(self.nsteps, lay.nsrc).contiguous()
+        if traces is None:
+            traces = torch.zeros((self.nsteps, max(0, lay.nrec)), dtype=torch.float32, device=self.device)
+        snaps = None
+        if saving_stride:
+            nsnap = self.nsteps // saving_stride
+            snaps = torch.zeros((nsnap,) + self.grid_shape, dtype=torch.float32, device=self.device)
+        ckpt = None
+        if checkpoint_every:
+            nck = (self.nsteps + checkpoint_every - 1) // checkpoint_every
+            ckpt = torch.zeros((nck, 2, lay.field_elems), dtype=torch.float32, device=self.device)
+        io = L.FwdIO()
+        io.workspace = _ptr(self.workspace).value
+        io.wavelet = _ptr(wavelet if lay.nsrc else None).value
+        io.field[0] = fields[0].data_ptr()
+        io.field[1] = fields[1].data_ptr()
+        io.traces = traces.data_ptr() if lay.nrec else None
+        io.snaps = snaps.data_ptr() if snaps is not None else None
+        io.saving_stride = int(saving_stride)
+        io.ckpt = ckpt.data_ptr() if ckpt is not None else None
+        io.ckpt_every = int(checkpoint_every)
+        io.step0 = int(step0)
+        io.nsteps_run = nrun
+        io.use_graph = 1 if use_graph else 0
+        if stencil_ms is not None:
+            assert stencil_ms.dtype.name == "float32" and stencil_ms.size >= nrun
+            io.stencil_ms = stencil_ms.ctypes.data_as(L.c_float_p)
+        self._keep = (wavelet, fields, traces, snaps, ckpt)
+        L.check("sw_forward", L.lib().sw_forward(self._plan, ctypes.byref(io), _stream()))
+        return ForwardResult(traces, fields, nrun % 2, snaps, ckpt, int(checkpoint_every))
+
+    def adjoint(self, wavelet, residual, ckpt, checkpoint_every, want_src_adjoint=False):
+        """Velocity gradient (physical grid) of 1/2 |traces - d_obs|^2 given the
+        residual dJ/dtraces and the forward checkpoints."""
+        lay = self.layout
+        fe = lay.field_elems
+        dev = self.device
+        work = [torch.empty(fe, dtype=torch.float32, device=dev) for _ in range(4)]
+        segment = torch.empty((checkpoint_every, fe), dtype=torch.float32, device=dev)
+        grad_m = torch.empty(fe, dtype=torch.float32, device=dev)
+        grad_vel = torch.empty(self.n, dtype=torch.float32, device=dev)
+        src_adj = None
+        if want_src_adjoint and lay.nsrc:
+            src_adj = torch.zeros((self.nsteps, lay.nsrc), dtype=torch.float32, device=dev)
+        residual = residual.to(dev, torch.float32).reshape(self.nsteps, lay.nrec).contiguous()
+        if lay.nsrc:
+            wavelet = wavelet.to(dev, torch.float32).reshape(self.nsteps, lay.nsrc).contiguous()
+        io = L.AdjIO()
+        io.workspace = _ptr(self.workspace).value
+        io.vel = self._vel.data_ptr()
+        io.wavelet = wavelet.data_ptr() if lay.nsrc else None
+        io.residual = residual.data_ptr()
+        io.ckpt = ckpt.data_ptr()
+        io.ckpt_every = int(checkpoint_every)
+        io.field[0], io.field[1] = work[0].data_ptr(), work[1].data_ptr()
+        io.adj[0], io.adj[1] = work[2].data_ptr(), work[3].data_ptr()
+        io.segment = segment.data_ptr()
+        io.grad_m = grad_m.data_ptr()
+        io.grad_vel = grad_vel.data_ptr()
+        io.src_adjoint = src_adj.data_ptr() if src_adj is not None else None
+        self._keep_adj = (work, segment, grad_m, residual, wavelet)
+        L.check("sw_adjoint", L.lib().sw_adjoint(self._plan, ctypes.byref(io), _stream()))
+        return grad_vel, src_adj, grad_m
+
+
+class AcousticForward(torch.autograd.Function):
+    """traces = F(vel); backward gives dJ/dvel by the hand-written adjoint with
+    checkpointed recomputation of the forward wavefield."""
+
+    @staticmethod
+    def forward(ctx, vel, prop, wavelet, checkpoint_every):
+        vel = vel.detach().to(prop.device, torch.float32).contiguous()
+        prop.prepare(vel)
+        res = prop.forward(wavelet, checkpoint_every=checkpoint_every)
+        ctx.prop = prop
+        ctx.vel = vel
+        ctx.wavelet = wavelet
+        ctx.ckpt = res.ckpt
+        ctx.every = checkpoint_every
+        return res.traces.clone()
+
+    @staticmethod
+    def backward(ctx, grad_traces):
+        prop = ctx.prop
+        if prop._vel is None or prop._vel.data_ptr() != ctx.vel.data_ptr():
+            prop.prepare(ctx.vel)      # the plan was re-prepared since this forward
+        g, _, _ = prop.adjoint(ctx.wavelet, grad_traces, ctx.ckpt, ctx.every)
+        return g, None, None, None

@@ -1,0 +1,150 @@
+"""Host-side checks of the C ABI (no GPU): every declared symbol is exported,
+host helpers and host tables agree with the oracle, invalid input is refused
+before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coeffs
+
+from paper_2201_05278_amd import _lib as L
+from paper_2201_05278_amd import Propagator, critical_dt, steps_for, ricker, SimwaveError
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "simwave_hip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 14
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(L.SIGNATURES), set(names) - set(L.SIGNATURES)
+    assert lib.sw_abi_version() == 1
+
+
+@pytest.mark.parametrize("ndim,h,so,cmax", [(2, 10.0, 2, 4700.0), (2, 10.0, 8, 4700.0),
+                                            (3, 20.0, 4, 6000.0), (3, 10.0, 16, 4500.0)])
+def test_critical_dt_and_steps_match_oracle(ndim, h, so, cmax):
+    a = critical_dt([h] * ndim, so, cmax)
+    b = coeffs.critical_dt([h] * ndim, so, cmax)
+    assert abs(a - b) <= 1e-14 * b
+    assert steps_for(2.0, a) == coeffs.steps_for(2.0, b)
+
+
+def test_ricker_matches_oracle():
+    dt = 5e-4
+    got = ricker(12.0, dt, 400).numpy()
+    ref = oracle.ricker(12.0, dt, 400)
+    assert np.max(np.abs(got - ref)) < 1e-7
+
+
+def _compare_tables(prop, prob, which, coords, interp, radius=4):
+    nodes, ids, w = prop.point_table(which)
+    ref_nodes, ref_ids, ref_w = oracle.geometry_table(prob, coords, interp, radius)
+    lay = prop.layout
+    # map padded-layout offsets back to extended-grid flat indices
+    off = nodes - lay.origin
+    if prop.ndim == 3:
+        p1, p2 = lay.padded[1], lay.padded[2]
+        z, r = np.divmod(off, p1 * p2)
+        x, y = np.divmod(r, p2)
+        flat = (z * lay.dims[1] + x) * lay.dims[2] + y
+    else:
+        z, x = np.divmod(off, lay.padded[1])
+        flat = z * lay.dims[1] + x
+    got = sorted(zip(ids.tolist(), flat.tolist(), w.tolist()))
+    ref = sorted(zip(ref_ids.tolist(), ref_nodes.tolist(), ref_w.tolist()))
+    assert [g[:2] for g in got] == [r[:2] for r in ref]
+    assert np.allclose([g[2] for g in got], [r[2] for r in ref], rtol=2e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("interp", ["hicks", "linear"])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_point_tables_match_oracle(interp, ndim):
+    n = (30, 41, 37)[:ndim]
+    h = (10.0, 12.0, 8.0)[:ndim]
+    nbl = ((5, 7), (6, 4), (3, 8))[:ndim]
+    prob = oracle.Problem(n=n, h=h, space_order=8, dt=1e-3, nsteps=10, nbl=nbl)
+    prop = Propagator(n, h, 8, 1e-3, 10, nbl=[list(x) for x in nbl])
+    rng = np.random.default_rng(1)
+    coords = rng.uniform(0.2, 0.8, size=(7, ndim)) * (np.array(n) - 1) * np.array(h)
+    coords[0] = (np.array(n) // 2) * np.array(h)          # an on-node point
+    prop.set_sources(coords, interp)
+    prop.set_receivers(coords[::-1], interp)
+    _compare_tables(prop, prob, "src", coords, interp)
+    _compare_tables(prop, prob, "rec", coords[::-1], interp)
+
+
+def test_layout_is_aligned_and_padded():
+    prop = Propagator((50, 60, 70), (10.0,) * 3, 8, 1e-3, 10, nbl=40)
+    lay = prop.layout
+    assert tuple(lay.dims) == (130, 140, 150)
+    assert lay.padded[2] % 64 == 0
+    assert lay.origin % 64 == 0                       # interior rows 256-byte aligned
+    assert lay.field_elems == lay.padded[0] * lay.padded[1] * lay.padded[2]
+    assert lay.halo == 4
+    p2 = Propagator((50, 60), (10.0, 10.0), 4, 1e-3, 10, nbl=[(0, 70), (70, 70)])
+    l2 = p2.layout
+    assert tuple(l2.dims[:2]) == (120, 200) and l2.padded[1] % 64 == 0
+
+
+def _expect(status_name, fn, *a, **k):
+    with pytest.raises(SimwaveError) as e:
+        fn(*a, **k)
+    assert L.STATUS[e.value.status] == status_name, str(e.value)
+
+
+def test_invalid_problems_refused():
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 20), (1.0, 1.0), 3, 1e-3, 5)
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 20), (1.0, 1.0), 18, 1e-3, 5)
+    _expect("SW_ERR_ARG", Propagator, (20, 20), (1.0, -1.0), 4, 1e-3, 5)
+    _expect("SW_ERR_ARG", Propagator, (20, 20), (1.0, 1.0), 4, -1e-3, 5)
+
+
+def test_mirror_ghosts_refused():
+    prob = L.Problem()
+    prob.ndim, prob.space_order, prob.dt, prob.nsteps = 2, 4, 1e-3, 5
+    prob.n[0] = prob.n[1] = 20
+    prob.h[0] = prob.h[1] = 1.0
+    prob.bc[0][0] = 1
+    h = ctypes.c_void_p()
+    st = L.lib().sw_plan_create(ctypes.byref(prob), ctypes.byref(h))
+    assert L.STATUS[st] == "SW_ERR_UNSUPPORTED"
+
+
+def test_points_outside_domain_refused():
+    prop = Propagator((20, 20), (10.0, 10.0), 4, 1e-3, 5, nbl=0)
+    _expect("SW_ERR_DOMAIN", prop.set_sources, [[-1.0, 50.0]])
+    _expect("SW_ERR_DOMAIN", prop.set_sources, [[15.0, 50.0]], "hicks", 4)   # footprint leaves grid
+    _expect("SW_ERR_ARG", prop.set_sources, [[100.0, 100.0]], "hicks", 3)    # no Kaiser b for r=3
+    prop.set_sources([[100.0, 100.0]], "hicks", 3, 4.0)
+    prop.set_sources([[0.0, 0.0]], "linear")
+
+
+def test_cfl_violation_refused_before_device_work():
+    prop = Propagator((20, 20), (10.0, 10.0), 8, 1e-2, 5, nbl=0)
+    lib = L.lib()
+    fake = ctypes.c_void_p(4096)
+    st = lib.sw_model_prepare(prop._plan, fake, None, 1500.0, fake, None)
+    assert L.STATUS[st] == "SW_ERR_CFL"
+    assert b"stability" in lib.sw_last_error()
+    st = lib.sw_model_prepare(prop._plan, fake, None, 1500.0, ctypes.c_void_p(4100), None)
+    assert L.STATUS[st] == "SW_ERR_WORKSPACE"
+
+
+def test_forward_before_prepare_refused():
+    prop = Propagator((20, 20), (10.0, 10.0), 4, 1e-3, 5, nbl=0)
+    io = L.FwdIO()
+    st = L.lib().sw_forward(prop._plan, ctypes.byref(io), None)
+    assert L.STATUS[st] == "SW_ERR_STATE"
