@@ -239,6 +239,51 @@ typedef struct sw_adj_io {
  * summed back from the layer onto the physical node it copies. */
 sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
 
+/* Override the stencil tiling of a plan: rows per tile `tx` and waves per
+ * block `nw` (constant density in 3D: (16,4), (8,4), (32,8) or (16,8); other
+ * schemes and 2D grids take 0, 0 for their fixed shape), z-chunk length `zc`
+ * (0: default) and `nt` (1: non-temporal loads and stores for the streamed
+ * arrays).  Results do not depend on the tiling.  tx = nw = zc = 0 and nt = -1
+ * restores the defaults. */
+sw_status sw_plan_set_tiling(sw_plan *plan, int32_t tx, int32_t nw, int32_t zc, int32_t nt);
+
+/* ---- batched shots and autotuning --------------------------------------- */
+
+typedef struct sw_batch sw_batch;
+
+/* Group `nshots` prepared constant-density plans (each with its own grid
+ * size, dt, model, geometry and workspace; all with the same ndim, space
+ * order and step count) so that every time step advances all shots with one
+ * persistent stencil launch over a tile list spanning all shots, one batched
+ * injection and one batched recording launch.  The plans stay owned by the
+ * caller and must outlive the batch. */
+sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out);
+sw_status sw_batch_destroy(sw_batch *batch);
+/* Bytes of the device descriptor table the caller allocates for the batch. */
+sw_status sw_batch_layout(const sw_batch *batch, int64_t *table_bytes);
+
+typedef struct sw_batch_io {
+    const sw_fwd_io *shots;   /* host array [nshots]: per-shot workspace, wavelet, field[2],
+                                 traces (snaps, ckpt, step0, nsteps_run ignored) */
+    void *table;              /* device, sw_batch_layout bytes, 256-byte aligned */
+    int32_t nsteps_run;       /* steps 0 .. nsteps_run-1 for every shot (fields cleared first) */
+    int32_t use_graph;        /* 1: capture the loop in a HIP graph and launch it */
+} sw_batch_io;
+
+/* Run the batch (enqueue only).  On return shot s has p^{nsteps_run} in
+ * shots[s].field[nsteps_run % 2]. */
+sw_status sw_batch_forward(sw_batch *batch, const sw_batch_io *io, void *stream);
+
+/* Pick the tile shape (rows per tile, waves per block), the z-chunk length and
+ * (for batches) the persistent grid size by timing a few steps of each
+ * candidate on the given buffers (their contents are overwritten), or reuse
+ * the choice stored under the same problem key in the JSON file `cache_path`
+ * (may be NULL: no cache).  The choice is kept in the plan / batch and
+ * written back to the cache.  Synchronises `stream`. */
+sw_status sw_plan_autotune(sw_plan *plan, const sw_fwd_io *io, const char *cache_path, void *stream);
+sw_status sw_batch_autotune(sw_batch *batch, const sw_batch_io *io, const char *cache_path,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,11 @@ class AdjIO(ctypes.Structure):
                 ("grad_m", c_void_p), ("grad_vel", c_void_p), ("src_adjoint", c_void_p)]
 
 
+class BatchIO(ctypes.Structure):
+    _fields_ = [("shots", ctypes.POINTER(FwdIO)), ("table", c_void_p), ("nsteps_run", c_int32),
+                ("use_graph", c_int32)]
+
+
 # every symbol the header declares, with its signature
 SIGNATURES = {
     "sw_abi_version": (c_int32, []),
@@ -82,6 +87,13 @@ SIGNATURES = {
     "sw_model_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "sw_forward": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), c_void_p]),
     "sw_adjoint": (c_int32, [c_void_p, ctypes.POINTER(AdjIO), c_void_p]),
+    "sw_plan_set_tiling": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
+    "sw_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "sw_batch_destroy": (c_int32, [c_void_p]),
+    "sw_batch_layout": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
+    "sw_batch_forward": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), c_void_p]),
+    "sw_plan_autotune": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), ctypes.c_char_p, c_void_p]),
+    "sw_batch_autotune": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), ctypes.c_char_p, c_void_p]),
 }
 
 _lib = None

@@ -8,25 +8,16 @@
 
 #include <hip/hip_runtime.h>
 
-#include "device.h"
-#include "plan.h"
+#include "runtime.h"
 
 namespace sw {
 const std::string &last_error();
-hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);
-hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
 }  // namespace sw
 
 using namespace sw;
 
-#define SW_HIP(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(SW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
-    } while (0)
 
-namespace {
+namespace sw {
 
 Geom make_geom(const sw_plan *p)
 {
@@ -37,17 +28,13 @@ Geom make_geom(const sw_plan *p)
     g.px = p->pad[1];
     g.py = p->pad[2];
     g.origin = p->origin;
+    g.xy0 = p->hx * p->pad[2] + kRowAlign;
+    g.base = p->origin - g.xy0;
     for (int i = 0; i < 3; ++i) {
         g.lo[i] = p->lo[i];
         g.np[i] = p->nphys[i];
     }
     return g;
-}
-
-template <typename T>
-T *at(void *ws, size_t off)
-{
-    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
 PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap::Pts &o, void *ws)
@@ -74,25 +61,40 @@ PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap
     return t;
 }
 
+bool const_shape_ok(int tx, int nw)
+{
+    return (tx == 16 && nw == 4) || (tx == 8 && nw == 4) || (tx == 32 && nw == 8) || (tx == 16 && nw == 8);
+}
+
+// z-chunk length giving about `want` blocks in total (at least 4R planes).
+int default_zc(const sw_plan *p, int tx, int64_t want)
+{
+    const int ntx = (p->dims[1] + tx - 1) / tx;
+    const int nty = (p->dims[2] + 63) / 64;
+    const int64_t tiles = int64_t(ntx) * nty;
+    const int nzc = int(std::max<int64_t>(1, (want + tiles - 1) / tiles));
+    const int zc = (p->dims[0] + nzc - 1) / nzc;
+    return std::max(zc, std::min(p->dims[0], 4 * p->r));
+}
+
 Tiling choose_tiling(const sw_plan *p)
 {
     Tiling t{};
     if (p->ndim == 2) {
         t.tx = 1;
         t.nw = 1;
+    } else if (p->prob.scheme != SW_CONST) {
+        t.tx = 16;      // variable-density kernels: 16 rows, 8 waves
+        t.nw = 8;
+    } else if (p->tile_tx) {
+        t.tx = p->tile_tx;
+        t.nw = p->tile_nw;
     } else {
         t.tx = (p->r <= 4) ? 16 : 8;
         t.nw = 4;
     }
-    // z chunks: enough blocks to fill 256 CUs several times over
-    const int ntx = (p->dims[1] + t.tx - 1) / t.tx;
-    const int nty = (p->dims[2] + 63) / 64;
-    const int64_t tiles = int64_t(ntx) * nty;
-    const int64_t want = (p->ndim == 2) ? 1024 : 2560;
-    int nzc = int(std::max<int64_t>(1, (want + tiles - 1) / tiles));
-    int zc = (p->dims[0] + nzc - 1) / nzc;
-    zc = std::max(zc, std::min(p->dims[0], 4 * p->r));
-    t.zc = zc;
+    t.zc = p->tile_zc ? std::min(p->tile_zc, p->dims[0]) : default_zc(p, t.tx, p->ndim == 2 ? 1024 : 2560);
+    t.nt = p->tile_nt;
     return t;
 }
 
@@ -167,7 +169,14 @@ sw_status check_problem(const sw_problem *q)
     return SW_OK;
 }
 
-}  // namespace
+sw_status check_prepared(const sw_plan *p, void *ws)
+{
+    if (!p->prepared) return fail(SW_ERR_STATE, "sw_model_prepare must run after the last geometry change");
+    if (ws != p->prepared_ws) return fail(SW_ERR_WORKSPACE, "workspace differs from the prepared one");
+    return SW_OK;
+}
+
+}  // namespace sw
 
 extern "C" {
 
@@ -247,7 +256,32 @@ sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
         p->prob.nbl[2][0] = p->prob.nbl[2][1] = 0;
     }
     build_layout(p);
+    if (int64_t(p->pad[1]) * p->pad[2] >= (int64_t(1) << 31)) {
+        delete p;
+        return fail(SW_ERR_UNSUPPORTED, "a z plane of the padded grid exceeds 2^31 elements");
+    }
     *out = p;
+    return SW_OK;
+}
+
+sw_status sw_plan_set_tiling(sw_plan *p, int32_t tx, int32_t nw, int32_t zc, int32_t nt)
+{
+    set_error("");
+    if (!p) return fail(SW_ERR_ARG, "plan is NULL");
+    if (zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
+    if (tx || nw) {
+        if (p->ndim != 3 || p->prob.scheme != SW_CONST)
+            return fail(SW_ERR_UNSUPPORTED, "this scheme / dimension has a fixed tile shape");
+        if (!const_shape_ok(tx, nw)) return fail(SW_ERR_UNSUPPORTED, "tile shape not provided");
+    }
+    p->tile_tx = tx;
+    p->tile_nw = nw;
+    p->tile_zc = zc;
+    p->tile_nt = nt < 0 ? 0 : (nt ? 1 : 0);
+    if (p->graph_exec) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
+        p->graph_exec = nullptr;
+    }
     return SW_OK;
 }
 
@@ -375,13 +409,6 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
     SW_HIP(launch_point_coef(table_dev(p, p->rec, p->ws.rec, ws), damp, vel, p->prob.dt, 1.0, s));
     p->prepared = true;
     p->prepared_ws = ws;
-    return SW_OK;
-}
-
-static sw_status check_prepared(const sw_plan *p, void *ws)
-{
-    if (!p->prepared) return fail(SW_ERR_STATE, "sw_model_prepare must run after the last geometry change");
-    if (ws != p->prepared_ws) return fail(SW_ERR_WORKSPACE, "workspace differs from the prepared one");
     return SW_OK;
 }
 

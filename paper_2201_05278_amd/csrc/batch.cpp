@@ -1,0 +1,465 @@
+// Batched shots (one persistent stencil launch per step over a tile list
+// spanning all shots, one batched injection and one batched recording) and the
+// autotuner of tile shape, z-chunk length, cache policy and persistent grid.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <limits>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace sw;
+
+struct sw_batch {
+    std::vector<sw_plan *> plans;
+    int nshots = 0;
+    int r = 4, ndim = 3, nsteps = 0;
+    Tiling tiling{16, 4, 64, 0};
+    int bpc = 0;                        // persistent blocks per CU (0: default)
+    int ncu = 256;
+    // host staging of the device table
+    std::vector<StencilParams> params;
+    std::vector<int> tile_start;
+    std::vector<ShotPoints> points;
+    size_t off_params = 0, off_tiles = 0, off_points = 0, table_bytes = 0;
+    int max_uniq = 0, max_per_node = 0, max_rec = 0, max_per_point = 0;
+    void *graph_exec = nullptr;
+    void *capture_stream = nullptr;
+    std::vector<uint64_t> graph_key;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+void batch_layout(sw_batch *b)
+{
+    b->off_params = 0;
+    b->off_tiles = align256(sizeof(StencilParams) * b->nshots);
+    b->off_points = b->off_tiles + align256(sizeof(int) * (b->nshots + 1));
+    b->table_bytes = b->off_points + align256(sizeof(ShotPoints) * b->nshots);
+}
+
+int persistent_blocks(const sw_batch *b)
+{
+    const int bpc = b->bpc > 0 ? b->bpc : (b->ndim == 2 ? 8 : 4);
+    return std::max(1, bpc * b->ncu);
+}
+
+// Fill the host table for the batch tiling and the io pointers.
+sw_status stage_table(sw_batch *b, const sw_batch_io *io)
+{
+    b->params.resize(b->nshots);
+    b->points.resize(b->nshots);
+    b->tile_start.assign(b->nshots + 1, 0);
+    b->max_uniq = b->max_per_node = b->max_rec = b->max_per_point = 0;
+    for (int s = 0; s < b->nshots; ++s) {
+        sw_plan *p = b->plans[s];
+        const sw_fwd_io &f = io->shots[s];
+        sw_status st = check_prepared(p, f.workspace);
+        if (st != SW_OK) return fail(st, "shot " + std::to_string(s) + ": " + sw_last_error());
+        if (!f.field[0] || !f.field[1] || f.field[0] == f.field[1])
+            return fail(SW_ERR_ARG, "shot " + std::to_string(s) + ": two distinct wavefield buffers are required");
+        if (p->src.count && !f.wavelet) return fail(SW_ERR_ARG, "shot " + std::to_string(s) + ": wavelet is NULL");
+        if (p->rec.count && !f.traces) return fail(SW_ERR_ARG, "shot " + std::to_string(s) + ": traces is NULL");
+        StencilParams &P = b->params[s];
+        fill_params(p, f.workspace, P);
+        Tiling t = b->tiling;
+        t.zc = std::min(t.zc, p->dims[0]);
+        set_tiles(p, t, P);
+        P.cur = f.field[0];
+        P.nxt = f.field[1];
+        b->tile_start[s + 1] = b->tile_start[s] + P.ntx * P.nty * P.nzc;
+        ShotPoints &sp = b->points[s];
+        sp.src = table_dev(p, p->src, p->ws.src, f.workspace);
+        sp.rec = table_dev(p, p->rec, p->ws.rec, f.workspace);
+        sp.field[0] = f.field[0];
+        sp.field[1] = f.field[1];
+        sp.wavelet = f.wavelet;
+        sp.traces = f.traces;
+        b->max_uniq = std::max(b->max_uniq, sp.src.nuniq);
+        b->max_per_node = std::max(b->max_per_node, sp.src.max_per_node);
+        b->max_rec = std::max(b->max_rec, sp.rec.count);
+        b->max_per_point = std::max(b->max_per_point, sp.rec.max_per_point);
+    }
+    return SW_OK;
+}
+
+sw_status upload_table(sw_batch *b, void *table, hipStream_t s)
+{
+    char *t = static_cast<char *>(table);
+    SW_HIP(hipMemcpyAsync(t + b->off_params, b->params.data(), sizeof(StencilParams) * b->nshots,
+                          hipMemcpyHostToDevice, s));
+    SW_HIP(hipMemcpyAsync(t + b->off_tiles, b->tile_start.data(), sizeof(int) * (b->nshots + 1),
+                          hipMemcpyHostToDevice, s));
+    SW_HIP(hipMemcpyAsync(t + b->off_points, b->points.data(), sizeof(ShotPoints) * b->nshots,
+                          hipMemcpyHostToDevice, s));
+    return SW_OK;
+}
+
+// One batched step k: stencil for every shot, then injection and recording.
+sw_status batch_step(sw_batch *b, void *table, int k, bool points, hipStream_t s)
+{
+    char *t = static_cast<char *>(table);
+    const auto *params = reinterpret_cast<const StencilParams *>(t + b->off_params);
+    const auto *tiles = reinterpret_cast<const int *>(t + b->off_tiles);
+    const auto *pts = reinterpret_cast<const ShotPoints *>(t + b->off_points);
+    SW_HIP(launch_const_batch(b->r, b->ndim, b->tiling, params, tiles, b->nshots, k % 2,
+                              persistent_blocks(b), s));
+    if (points) {
+        SW_HIP(launch_inject_batch(pts, b->nshots, b->max_uniq, b->max_per_node, k, k % 2, s));
+        SW_HIP(launch_record_batch(pts, b->nshots, b->max_rec, b->max_per_point, k, k % 2, s));
+    }
+    return SW_OK;
+}
+
+sw_status enqueue_batch(sw_batch *b, const sw_batch_io *io, hipStream_t s)
+{
+    for (int i = 0; i < b->nshots; ++i) {
+        const sw_fwd_io &f = io->shots[i];
+        SW_HIP(launch_fill(f.field[0], b->plans[i]->field_elems, 0.0f, s));
+        SW_HIP(launch_fill(f.field[1], b->plans[i]->field_elems, 0.0f, s));
+    }
+    for (int k = 0; k < io->nsteps_run; ++k) {
+        sw_status st = batch_step(b, io->table, k, true, s);
+        if (st != SW_OK) return st;
+    }
+    return SW_OK;
+}
+
+// ---- a small JSON cache: {"key": {"tx": 16, "nw": 4, "zc": 74, "nt": 1, "bpc": 4}, ...}
+std::map<std::string, std::map<std::string, int>> read_cache(const char *path)
+{
+    std::map<std::string, std::map<std::string, int>> out;
+    if (!path) return out;
+    std::ifstream in(path);
+    if (!in) return out;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string txt = ss.str();
+    size_t pos = 0;
+    while (true) {
+        const size_t k0 = txt.find('"', pos);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = txt.find('"', k0 + 1);
+        const size_t b0 = txt.find('{', k1);
+        const size_t b1 = txt.find('}', b0);
+        if (k1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+        const std::string key = txt.substr(k0 + 1, k1 - k0 - 1);
+        const std::string body = txt.substr(b0 + 1, b1 - b0 - 1);
+        std::map<std::string, int> vals;
+        size_t q = 0;
+        while (true) {
+            const size_t a0 = body.find('"', q);
+            if (a0 == std::string::npos) break;
+            const size_t a1 = body.find('"', a0 + 1);
+            const size_t c = body.find(':', a1);
+            if (a1 == std::string::npos || c == std::string::npos) break;
+            vals[body.substr(a0 + 1, a1 - a0 - 1)] = std::atoi(body.c_str() + c + 1);
+            q = c + 1;
+        }
+        out[key] = vals;
+        pos = b1 + 1;
+    }
+    return out;
+}
+
+void write_cache(const char *path, const std::map<std::string, std::map<std::string, int>> &c)
+{
+    if (!path) return;
+    std::ofstream o(path);
+    o << "{\n";
+    size_t n = 0;
+    for (const auto &kv : c) {
+        o << "  \"" << kv.first << "\": {";
+        size_t m = 0;
+        for (const auto &f : kv.second) o << "\"" << f.first << "\": " << f.second << (++m < kv.second.size() ? ", " : "");
+        o << "}" << (++n < c.size() ? ",\n" : "\n");
+    }
+    o << "}\n";
+}
+
+std::string plan_key(const sw_plan *p, const char *kind)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%s_s%d_r%d_d%d_%dx%dx%d", kind, p->prob.scheme, p->r, p->ndim,
+                  p->dims[0], p->dims[1], p->dims[2]);
+    return buf;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+}
+
+std::vector<int> zc_candidates(int Z, int r)
+{
+    std::vector<int> out;
+    for (int nz : {1, 2, 4, 8, 16}) {
+        const int zc = (Z + nz - 1) / nz;
+        if (zc >= 4 * r || nz == 1) out.push_back(zc);
+    }
+    for (int zc : {32, 48, 64, 96})
+        if (zc < Z && zc >= 4 * r) out.push_back(zc);
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out)
+{
+    set_error("");
+    if (!out || !plans || nshots < 1) return fail(SW_ERR_ARG, "bad arguments");
+    *out = nullptr;
+    const sw_plan *p0 = plans[0];
+    for (int s = 0; s < nshots; ++s) {
+        const sw_plan *p = plans[s];
+        if (!p) return fail(SW_ERR_ARG, "plan is NULL");
+        if (p->prob.scheme != SW_CONST)
+            return fail(SW_ERR_UNSUPPORTED, "batches cover the constant-density scheme");
+        if (p->ndim != p0->ndim || p->r != p0->r || p->prob.nsteps != p0->prob.nsteps)
+            return fail(SW_ERR_ARG, "all shots need the same ndim, space order and step count");
+    }
+    sw_batch *b = new (std::nothrow) sw_batch();
+    if (!b) return fail(SW_ERR_ARG, "out of host memory");
+    b->plans.assign(plans, plans + nshots);
+    b->nshots = nshots;
+    b->r = p0->r;
+    b->ndim = p0->ndim;
+    b->nsteps = p0->prob.nsteps;
+    b->tiling = Tiling{p0->ndim == 2 ? 1 : 16, p0->ndim == 2 ? 1 : 4, 64, 0};
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        b->ncu = ncu;
+    batch_layout(b);
+    *out = b;
+    return SW_OK;
+}
+
+sw_status sw_batch_destroy(sw_batch *b)
+{
+    set_error("");
+    if (!b) return SW_OK;
+    if (b->graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(b->graph_exec));
+    if (b->capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(b->capture_stream));
+    delete b;
+    return SW_OK;
+}
+
+sw_status sw_batch_layout(const sw_batch *b, int64_t *table_bytes)
+{
+    set_error("");
+    if (!b || !table_bytes) return fail(SW_ERR_ARG, "NULL argument");
+    *table_bytes = int64_t(b->table_bytes);
+    return SW_OK;
+}
+
+sw_status sw_batch_forward(sw_batch *b, const sw_batch_io *io, void *stream)
+{
+    set_error("");
+    if (!b || !io || !io->shots || !io->table) return fail(SW_ERR_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(io->table) % 256) return fail(SW_ERR_WORKSPACE, "table must be 256-byte aligned");
+    if (io->nsteps_run < 0 || io->nsteps_run > b->nsteps) return fail(SW_ERR_ARG, "nsteps_run outside [0, nsteps]");
+    sw_status st = stage_table(b, io);
+    if (st != SW_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = upload_table(b, io->table, s);
+    if (st != SW_OK) return st;
+    if (!io->use_graph) return enqueue_batch(b, io, s);
+
+    std::vector<uint64_t> key = {uint64_t(uintptr_t(io->table)), uint64_t(io->nsteps_run),
+                                 uint64_t(b->tiling.tx), uint64_t(b->tiling.nw), uint64_t(b->tiling.zc),
+                                 uint64_t(b->tiling.nt), uint64_t(b->bpc)};
+    for (int i = 0; i < b->nshots; ++i) {
+        const sw_fwd_io &f = io->shots[i];
+        for (const void *ptr : {static_cast<const void *>(f.workspace), static_cast<const void *>(f.wavelet),
+                                static_cast<const void *>(f.field[0]), static_cast<const void *>(f.field[1]),
+                                static_cast<const void *>(f.traces)})
+            key.push_back(uint64_t(uintptr_t(ptr)));
+    }
+    if (!b->graph_exec || b->graph_key != key) {
+        if (b->graph_exec) {
+            (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(b->graph_exec));
+            b->graph_exec = nullptr;
+        }
+        if (!b->capture_stream) {
+            hipStream_t cs = nullptr;
+            SW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            b->capture_stream = cs;
+        }
+        hipStream_t cs = static_cast<hipStream_t>(b->capture_stream);
+        SW_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        st = enqueue_batch(b, io, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (st != SW_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(SW_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        b->graph_exec = exec;
+        b->graph_key = key;
+    }
+    SW_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(b->graph_exec), s));
+    return SW_OK;
+}
+
+sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_path, void *stream)
+{
+    set_error("");
+    if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
+    sw_status st = check_prepared(p, io->workspace);
+    if (st != SW_OK) return st;
+    if (!io->field[0] || !io->field[1] || io->field[0] == io->field[1])
+        return fail(SW_ERR_ARG, "two distinct wavefield buffers are required");
+    const std::string key = plan_key(p, "plan");
+    auto cache = read_cache(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        auto &v = it->second;
+        return sw_plan_set_tiling(p, v["tx"], v["nw"], v["zc"], v["nt"]);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<std::pair<int, int>> shapes;
+    if (p->ndim == 3 && p->prob.scheme == SW_CONST) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}};
+    else shapes = {{0, 0}};
+    hipEvent_t e0, e1;
+    SW_HIP(hipEventCreate(&e0));
+    SW_HIP(hipEventCreate(&e1));
+    float best = std::numeric_limits<float>::max();
+    int bt[4] = {0, 0, 0, 0};
+    StencilParams P;
+    fill_params(p, io->workspace, P);
+    P.cur = io->field[0];
+    P.nxt = io->field[1];
+    for (auto sh : shapes)
+        for (int zc : zc_candidates(p->dims[0], p->r))
+            for (int nt : {0, 1}) {
+                st = sw_plan_set_tiling(p, sh.first, sh.second, zc, nt);
+                if (st != SW_OK) continue;
+                for (int w = 0; w < 2; ++w) SW_HIP(stencil(p, MODE_FWD, P, s));
+                SW_HIP(hipEventRecord(e0, s));
+                const int reps = 5;
+                for (int k = 0; k < reps; ++k) SW_HIP(stencil(p, MODE_FWD, P, s));
+                SW_HIP(hipEventRecord(e1, s));
+                SW_HIP(hipEventSynchronize(e1));
+                const float ms = elapsed(e0, e1) / reps;
+                if (ms < best) {
+                    best = ms;
+                    bt[0] = sh.first; bt[1] = sh.second; bt[2] = zc; bt[3] = nt;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = sw_plan_set_tiling(p, bt[0], bt[1], bt[2], bt[3]);
+    if (st != SW_OK) return st;
+    cache[key] = {{"tx", bt[0]}, {"nw", bt[1]}, {"zc", bt[2]}, {"nt", bt[3]}};
+    write_cache(cache_path, cache);
+    return SW_OK;
+}
+
+sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cache_path, void *stream)
+{
+    set_error("");
+    if (!b || !io || !io->shots || !io->table) return fail(SW_ERR_ARG, "NULL argument");
+    int64_t nodes = 0;
+    int zmin = std::numeric_limits<int>::max();
+    for (auto *p : b->plans) {
+        nodes += p->grid_nodes;
+        zmin = std::min(zmin, p->dims[0]);
+    }
+    char kb[128];
+    std::snprintf(kb, sizeof(kb), "batch_r%d_d%d_n%d_g%lld", b->r, b->ndim, b->nshots,
+                  static_cast<long long>(nodes >> 20));
+    const std::string key = kb;
+    auto cache = read_cache(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        auto &v = it->second;
+        if (b->ndim == 2 || const_shape_ok(v["tx"], v["nw"])) {
+            b->tiling = Tiling{v["tx"], v["nw"], v["zc"], v["nt"]};
+            b->bpc = v["bpc"];
+            return SW_OK;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<std::pair<int, int>> shapes;
+    if (b->ndim == 3) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}};
+    else shapes = {{1, 1}};
+    hipEvent_t e0, e1;
+    SW_HIP(hipEventCreate(&e0));
+    SW_HIP(hipEventCreate(&e1));
+    auto time_cfg = [&](float &ms) -> sw_status {
+        sw_status st = stage_table(b, io);
+        if (st != SW_OK) return st;
+        st = upload_table(b, io->table, s);
+        if (st != SW_OK) return st;
+        for (int w = 0; w < 1; ++w) {
+            st = batch_step(b, io->table, w, false, s);
+            if (st != SW_OK) return st;
+        }
+        SW_HIP(hipEventRecord(e0, s));
+        const int reps = 3;
+        for (int k = 0; k < reps; ++k) {
+            st = batch_step(b, io->table, k + 1, false, s);
+            if (st != SW_OK) return st;
+        }
+        SW_HIP(hipEventRecord(e1, s));
+        SW_HIP(hipEventSynchronize(e1));
+        ms = elapsed(e0, e1) / reps;
+        return SW_OK;
+    };
+    float best = std::numeric_limits<float>::max();
+    Tiling bt = b->tiling;
+    int bbpc = 0;
+    // tile shape, z chunk and cache policy at the default grid, then the grid size
+    for (auto sh : shapes)
+        for (int zc : zc_candidates(zmin, b->r))
+            for (int nt : {0, 1}) {
+                b->tiling = Tiling{sh.first, sh.second, zc, nt};
+                b->bpc = 0;
+                float ms = 0.0f;
+                sw_status st = time_cfg(ms);
+                if (st != SW_OK) return st;
+                if (ms < best) {
+                    best = ms;
+                    bt = b->tiling;
+                }
+            }
+    b->tiling = bt;
+    for (int bpc : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        b->bpc = bpc;
+        float ms = 0.0f;
+        sw_status st = time_cfg(ms);
+        if (st != SW_OK) return st;
+        if (ms < best) {
+            best = ms;
+            bbpc = bpc;
+        }
+    }
+    b->bpc = bbpc;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cache[key] = {{"tx", bt.tx}, {"nw", bt.nw}, {"zc", bt.zc}, {"nt", bt.nt}, {"bpc", bbpc}};
+    write_cache(cache_path, cache);
+    return SW_OK;
+}
+
+}  // extern "C"

@@ -12,6 +12,8 @@ struct Geom {
     int Z, X, Y;            // extended grid extents
     int px, py;             // padded x extent and row pitch
     int64_t origin;         // element offset of node (0, 0, 0)
+    int64_t base;           // element offset of the first padded element of plane z = 0
+    int xy0;                // in-plane offset of node (x, y) = (0, 0) from that element
     int lo[3];              // layer width on the low side (physical box start)
     int np[3];              // physical extents
 };
@@ -22,6 +24,16 @@ __host__ __device__ inline int64_t elem(const Geom &g, int z, int x, int y)
 }
 
 enum StencilMode { MODE_FWD = 0, MODE_STORE = 1, MODE_IMAGE = 2 };
+
+// Blocks are dealt round-robin to the 8 XCDs; remap the flat block index so
+// that each XCD receives a contiguous range of tiles (neighbouring tiles then
+// share halos through the same L2).  A bijection on [0, n).
+__device__ inline int xcd_remap(int bid, int n)
+{
+    const int per = n / 8, rem = n % 8;
+    const int xcd = bid % 8, k = bid / 8;
+    return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
 
 struct StencilParams {
     float *nxt;             // p^{n-1} on entry, p^{n+1} on exit (in place)
@@ -44,10 +56,11 @@ struct Tiling {
     int tx;                 // rows (x) per tile
     int nw;                 // waves per block
     int zc;                 // z-chunk length
+    int nt;                 // 1: non-temporal loads/stores for the streamed arrays
 };
 
-hipError_t launch_stencil(int scheme, int r, int ndim, int mode, const Tiling &t,
-                          StencilParams &P, hipStream_t s);
+hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);
+hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
 
 // ---- point and utility kernels ----
 struct PointTableDev {
@@ -65,6 +78,25 @@ struct PointTableDev {
     float *wscaled;
     int count, nent, nuniq, max_per_point, max_per_node;
 };
+
+// Points of one shot of a batch: tables, the shot's two wavefield buffers,
+// wavelet [nsteps][nsrc] and traces [nsteps][nrec].
+struct ShotPoints {
+    PointTableDev src, rec;
+    float *field[2];
+    const float *wavelet;
+    float *traces;
+};
+
+hipError_t launch_const_batch(int r, int ndim, const Tiling &t, const StencilParams *shots,
+                              const int *tile_start, int nshots, int parity, int nblocks,
+                              hipStream_t s);
+// Injection / recording for every shot of a batch at step `step`; the new
+// level is in field[parity ^ 1].
+hipError_t launch_inject_batch(const ShotPoints *shots, int nshots, int max_uniq, int max_per_node,
+                               int step, int parity, hipStream_t s);
+hipError_t launch_record_batch(const ShotPoints *shots, int nshots, int max_count, int max_per_point,
+                               int step, int parity, hipStream_t s);
 
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);

@@ -124,6 +124,42 @@ __global__ void __launch_bounds__(kBlock) k_record(PointTableDev t, const float 
     if (pt < t.count && sub == 0) out[pt] = acc;
 }
 
+// Batched versions: blockIdx.y selects the shot.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_inject_batch(const ShotPoints *__restrict__ shots, int step,
+                                                         int parity)
+{
+    const ShotPoints &S = shots[blockIdx.y];
+    const PointTableDev &t = S.src;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = gid / G, sub = gid % G;
+    const float *amp = S.wavelet + size_t(step) * t.count;
+    float sa = 0.0f;
+    if (u < t.nuniq)
+        for (int k = t.uptr[u] + sub; k < t.uptr[u + 1]; k += G) {
+            const int e = t.uent[k];
+            sa += t.coef_a[e] * amp[t.pid[e]];
+        }
+    sa = group_sum<G>(sa);
+    if (u < t.nuniq && sub == 0) S.field[parity ^ 1][t.unode[u]] += sa;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_record_batch(const ShotPoints *__restrict__ shots, int step,
+                                                         int parity)
+{
+    const ShotPoints &S = shots[blockIdx.y];
+    const PointTableDev &t = S.rec;
+    const float *field = S.field[parity ^ 1];
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pt = gid / G, sub = gid % G;
+    float acc = 0.0f;
+    if (pt < t.count)
+        for (int e = t.ptr[pt] + sub; e < t.ptr[pt + 1]; e += G) acc += t.wscaled[e] * field[t.node[e]];
+    acc = group_sum<G>(acc);
+    if (pt < t.count && sub == 0) S.traces[size_t(step) * t.count + pt] = acc;
+}
+
 __global__ void k_snapshot(Geom g, const float *__restrict__ f, float *__restrict__ out)
 {
     const int64_t total = int64_t(g.Z) * g.X * g.Y;
@@ -250,6 +286,35 @@ hipError_t launch_record(const PointTableDev &t, const float *field, float *out,
     if (t.count <= 0) return hipSuccess;
     const int G = group_size(t.max_per_point);
     SW_GROUP_DISPATCH(G, k_record, t.count, s, t, field, out);
+    return hipGetLastError();
+}
+
+#define SW_GROUP_DISPATCH2(G, KERNEL, N, NY, ...)                                                \
+    switch (G) {                                                                                  \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(blocks_exact(int64_t(N) * 1), NY), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(blocks_exact(int64_t(N) * 2), NY), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(blocks_exact(int64_t(N) * 4), NY), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, dim3(blocks_exact(int64_t(N) * 8), NY), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, dim3(blocks_exact(int64_t(N) * 16), NY), dim3(kBlock), 0, __VA_ARGS__); break; \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(blocks_exact(int64_t(N) * 32), NY), dim3(kBlock), 0, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<64>, dim3(blocks_exact(int64_t(N) * 64), NY), dim3(kBlock), 0, __VA_ARGS__); break; \
+    }
+
+hipError_t launch_inject_batch(const ShotPoints *shots, int nshots, int max_uniq, int max_per_node,
+                               int step, int parity, hipStream_t s)
+{
+    if (max_uniq <= 0 || nshots <= 0) return hipSuccess;
+    const int G = group_size(max_per_node);
+    SW_GROUP_DISPATCH2(G, k_inject_batch, max_uniq, nshots, s, shots, step, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_batch(const ShotPoints *shots, int nshots, int max_count, int max_per_point,
+                               int step, int parity, hipStream_t s)
+{
+    if (max_count <= 0 || nshots <= 0) return hipSuccess;
+    const int G = group_size(max_per_point);
+    SW_GROUP_DISPATCH2(G, k_record_batch, max_count, nshots, s, shots, step, parity);
     return hipGetLastError();
 }
 

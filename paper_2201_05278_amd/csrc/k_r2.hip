@@ -1,0 +1,23 @@
+// Stencil kernels instantiated for radius 2 (space order 4).
+#include "stencil_const.h"
+#include "stencil_vd.h"
+
+namespace sw {
+
+hipError_t launch_const_r2(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
+{
+    return launch_const_radius<2>(ndim, mode, t, P, s);
+}
+
+hipError_t launch_batch_r2(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
+                            int nshots, int parity, int nblocks, hipStream_t s)
+{
+    return launch_batch_radius<2>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+}
+
+hipError_t launch_vd_r2(int scheme, int ndim, StencilParams &P, hipStream_t s)
+{
+    return launch_vd_radius<2>(scheme, ndim, P, s);
+}
+
+}  // namespace sw

@@ -1,0 +1,23 @@
+// Stencil kernels instantiated for radius 8 (space order 16).
+#include "stencil_const.h"
+#include "stencil_vd.h"
+
+namespace sw {
+
+hipError_t launch_const_r8(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
+{
+    return launch_const_radius<8>(ndim, mode, t, P, s);
+}
+
+hipError_t launch_batch_r8(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
+                            int nshots, int parity, int nblocks, hipStream_t s)
+{
+    return launch_batch_radius<8>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+}
+
+hipError_t launch_vd_r8(int scheme, int ndim, StencilParams &P, hipStream_t s)
+{
+    return launch_vd_radius<8>(scheme, ndim, P, s);
+}
+
+}  // namespace sw

@@ -85,6 +85,8 @@ struct sw_plan {
     sw::WorkspaceMap ws;
     bool prepared = false;
     void *prepared_ws = nullptr;
+    // stencil tiling chosen by sw_plan_set_tiling / sw_plan_autotune (tx == 0: default)
+    int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = 0;
     // cached HIP graph of a forward run, captured on a private stream
     void *graph_exec = nullptr;
     void *capture_stream = nullptr;

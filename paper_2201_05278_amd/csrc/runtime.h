@@ -1,0 +1,36 @@
+// Host runtime helpers shared by the C ABI translation units.
+#pragma once
+
+#include <string>
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "plan.h"
+
+#define SW_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return sw::fail(SW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+namespace sw {
+
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+Geom make_geom(const sw_plan *p);
+PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap::Pts &o, void *ws);
+bool const_shape_ok(int tx, int nw);
+int default_zc(const sw_plan *p, int tx, int64_t want);
+Tiling choose_tiling(const sw_plan *p);
+void fill_params(const sw_plan *p, void *ws, StencilParams &P);
+void set_tiles(const sw_plan *p, const Tiling &t, StencilParams &P);
+hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s);
+sw_status check_prepared(const sw_plan *p, void *ws);
+
+}  // namespace sw

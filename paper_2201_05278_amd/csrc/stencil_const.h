@@ -1,0 +1,327 @@
+// Constant-density leapfrog stencil (paper, "Time discretization" update with
+// the "Space discretization" centred second derivatives), damping fused:
+//
+//   p^{n+1} = A (2 p^n + K (L p^n)) - B p^{n-1},
+//   L p = c0 p + sum_j [cz_j (p_{z+j} + p_{z-j}) + cx_j (...) + cy_j (...)],
+//
+// with (A, B) looked up from the squared layer distance of the node (1, 1 in
+// the physical grid), so no damping array is read.
+//
+// Blocking: a block owns a TX x 64 tile of the (x, y) plane (y, the
+// contiguous axis, across the 64 lanes of a wavefront) and marches along z
+// through a chunk of planes.  Each thread keeps the 2R+1 values of its column
+// p[z-R .. z+R] in a register queue; the current plane of the tile plus an
+// R-wide halo in x and y is staged in LDS (double buffered, one barrier per
+// plane) for the in-plane neighbours.  Loads for plane z+1 are issued before
+// plane z is computed.  Grid points outside the extended grid read as zero.
+// Addresses are a per-plane base pointer (uniform) plus an unsigned 32-bit
+// lane offset.  With NT = 1 the streamed arrays (p^{n-1}, K and the output)
+// use non-temporal loads and stores so that the caches keep the p^n planes
+// that neighbouring tiles re-read as halos.
+//
+// Modes: MODE_FWD plain step; MODE_STORE also writes K (L p) (the recomputed
+// forward level of the imaging condition); MODE_IMAGE also accumulates
+// grad += p * store / K^2 (zero-lag imaging of the adjoint field p against the
+// stored level).
+#pragma once
+
+#include "device.h"
+
+namespace sw {
+
+template <int NT>
+__device__ __forceinline__ float ld_stream(const float *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <int NT>
+__device__ __forceinline__ void st_stream(float v, float *p)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// One tile (TX x 64 columns, one z chunk) of one grid; `bid` is the tile's
+// index in (z chunk, x tile, y tile) order.
+template <int R, int NDIM, int TX, int NW, int MODE, int NT>
+__device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
+{
+    static_assert(TX % NW == 0, "rows must split evenly over waves");
+    constexpr int RPT = TX / NW;                 // rows per thread
+    constexpr int HXR = (NDIM == 3) ? R : 0;     // LDS halo rows in x
+    constexpr int LY = 64 + 2 * R;
+    constexpr int LX = TX + 2 * HXR;
+    constexpr int NTH = 64 * NW;
+    constexpr int HXN = (NDIM == 3) ? (2 * R + NW - 1) / NW : 0;   // x-halo rows per wave
+    constexpr int YHN = (TX * 2 * R + NTH - 1) / NTH;               // y-halo items per thread
+    __shared__ float lds[2][LX][LY];
+
+    const Geom &g = P.g;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ty = bid % P.nty;
+    const int rest = bid / P.nty;
+    const int tx = rest % P.ntx;
+    const int zc = rest / P.ntx;
+    const int y0 = ty * 64;
+    const int y = y0 + lane;
+    const int x0 = tx * TX;
+    const int zb = zc * P.zc;
+    const int ze = min(zb + P.zc, g.Z);
+    const int64_t sz = int64_t(g.px) * g.py;
+    const bool yin = y < g.Y;
+    const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
+    // lane offsets inside a z plane: off(x, y) = xy0 + x py + y >= 0
+    auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
+    const float *cur0 = P.cur + g.base;
+    float *nxt0 = P.nxt + g.base;
+    const float *k0 = P.K + g.base;
+
+    unsigned ro[RPT];
+    bool rin[RPT];
+    int ex2[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int x = x0 + wave * RPT + i;
+        rin[i] = yin && x < g.X;
+        ro[i] = off(x, y);
+        const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
+        ex2[i] = ex * ex + ey * ey;
+    }
+    unsigned hxo[HXN > 0 ? HXN : 1];
+    bool hxin[HXN > 0 ? HXN : 1], hxok[HXN > 0 ? HXN : 1];
+    int hxrow[HXN > 0 ? HXN : 1];
+#pragma unroll
+    for (int s = 0; s < HXN; ++s) {
+        const int hr = wave + s * NW;
+        hxok[s] = hr < 2 * R;
+        const int x = (hr < R) ? x0 - R + hr : x0 + TX + hr - R;
+        hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
+        hxrow[s] = (hr < R) ? hr : TX + hr;
+        hxo[s] = hxin[s] ? off(x, y) : 0u;
+    }
+    unsigned hyo[YHN];
+    bool hyin[YHN], hyok[YHN];
+    int hyrow[YHN], hycol[YHN];
+#pragma unroll
+    for (int s = 0; s < YHN; ++s) {
+        const int e = threadIdx.x + s * NTH;
+        hyok[s] = e < TX * 2 * R;
+        const int row = e / (2 * R), c = e % (2 * R);
+        const int yy = (c < R) ? y0 - R + c : y0 + 64 + c - R;
+        const int x = x0 + row;
+        hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
+        hyrow[s] = HXR + row;
+        hycol[s] = (c < R) ? c : 64 + c;
+        hyo[s] = hyin[s] ? off(x, yy) : 0u;
+    }
+
+    float q[RPT][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+        const int z = zb - R + k;
+        const bool zin = z >= 0 && z < g.Z;
+        const float *pl = cur0 + int64_t(z) * sz;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) q[i][k] = (rin[i] && zin) ? pl[ro[i]] : 0.0f;
+    }
+
+    // registers filled one plane ahead
+    float nf[RPT], np_[RPT], nk[RPT], na[RPT], nb[RPT], nd[RPT], ng[RPT];
+    float nhx[HXN > 0 ? HXN : 1], nhy[YHN];
+    auto load = [&](int z) {
+        const int zf = z + R;
+        const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
+        const float *pc = cur0 + int64_t(z) * sz;
+        const float *pf = cur0 + int64_t(zf) * sz;
+        const float *pn = nxt0 + int64_t(z) * sz;
+        const float *pk = k0 + int64_t(z) * sz;
+        const bool fin = zf < g.Z;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            nf[i] = (rin[i] && fin) ? pf[ro[i]] : 0.0f;
+            np_[i] = rin[i] ? ld_stream<NT>(pn + ro[i]) : 0.0f;
+            nk[i] = rin[i] ? ld_stream<NT>(pk + ro[i]) : 0.0f;
+            const int d2 = ez * ez + ex2[i];
+            na[i] = 1.0f;
+            nb[i] = 1.0f;
+            if (rin[i] && d2 > 0) {
+                const float2 ab = P.damp[d2];
+                na[i] = ab.x;
+                nb[i] = ab.y;
+            }
+            if constexpr (MODE == MODE_IMAGE) {
+                const int64_t o = int64_t(z) * sz + g.base + ro[i];
+                nd[i] = rin[i] ? ld_stream<NT>(P.store + o) : 0.0f;
+                ng[i] = rin[i] ? ld_stream<NT>(P.grad + o) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < HXN; ++s) nhx[s] = hxin[s] ? pc[hxo[s]] : 0.0f;
+#pragma unroll
+        for (int s = 0; s < YHN; ++s) nhy[s] = hyin[s] ? pc[hyo[s]] : 0.0f;
+    };
+
+    load(zb);
+    int buf = 0;
+    for (int z = zb; z < ze; ++z) {
+        float pp[RPT], pk[RPT], pa[RPT], pb[RPT], pd[RPT], pg[RPT];
+        float hx[HXN > 0 ? HXN : 1], hy[YHN];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            q[i][2 * R] = nf[i];
+            pp[i] = np_[i];
+            pk[i] = nk[i];
+            pa[i] = na[i];
+            pb[i] = nb[i];
+            if constexpr (MODE == MODE_IMAGE) {
+                pd[i] = nd[i];
+                pg[i] = ng[i];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < HXN; ++s) hx[s] = nhx[s];
+#pragma unroll
+        for (int s = 0; s < YHN; ++s) hy[s] = nhy[s];
+        if (z + 1 < ze) load(z + 1);
+
+        float(*T)[LY] = lds[buf];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) T[HXR + wave * RPT + i][R + lane] = q[i][R];
+#pragma unroll
+        for (int s = 0; s < HXN; ++s)
+            if (hxok[s]) T[hxrow[s]][R + lane] = hx[s];
+#pragma unroll
+        for (int s = 0; s < YHN; ++s)
+            if (hyok[s]) T[hyrow[s]][hycol[s]] = hy[s];
+        __syncthreads();
+
+        float *pn = nxt0 + int64_t(z) * sz;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int lx = HXR + wave * RPT + i, ly = R + lane;
+            const float c = q[i][R];
+            float lap = P.c0 * c;
+#pragma unroll
+            for (int j = 1; j <= R; ++j) lap = fmaf(P.cz[j], q[i][R + j] + q[i][R - j], lap);
+            if constexpr (NDIM == 3) {
+#pragma unroll
+                for (int j = 1; j <= R; ++j) lap = fmaf(P.cx[j], T[lx + j][ly] + T[lx - j][ly], lap);
+            }
+#pragma unroll
+            for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[lx][ly + j] + T[lx][ly - j], lap);
+            const float out = pa[i] * fmaf(pk[i], lap, 2.0f * c) - pb[i] * pp[i];
+            if (rin[i]) {
+                st_stream<NT>(out, pn + ro[i]);
+                const int64_t o = int64_t(z) * sz + g.base + ro[i];
+                if constexpr (MODE == MODE_STORE) st_stream<NT>(pk[i] * lap, P.store + o);
+                if constexpr (MODE == MODE_IMAGE)
+                    st_stream<NT>(fmaf(c, pd[i] / (pk[i] * pk[i]), pg[i]), P.grad + o);
+            }
+        }
+        buf ^= 1;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) q[i][k] = q[i][k + 1];
+    }
+}
+
+template <int R, int NDIM, int TX, int NW, int MODE, int NT>
+__global__ void __launch_bounds__(64 * NW) k_const(StencilParams P)
+{
+    const_tile<R, NDIM, TX, NW, MODE, NT>(P, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Many grids (shots) in one persistent launch: the tiles of all shots form
+// one list (shot s owns [tile_start[s], tile_start[s+1])); each block takes
+// tiles blockIdx, blockIdx + gridDim, ... (XCD-aware), looks up the shot and
+// runs the same tile code on that shot's arrays.  `parity` swaps the two
+// wavefield buffers of every shot.
+template <int R, int NDIM, int TX, int NW, int NT>
+__global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__restrict__ shots,
+                                                         const int *__restrict__ tile_start,
+                                                         int nshots, int parity)
+{
+    const int total = tile_start[nshots];
+    const int first = xcd_remap(blockIdx.x, gridDim.x);
+    for (int t = first; t < total; t += gridDim.x) {
+        int lo = 0, hi = nshots - 1;          // last shot with tile_start <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        StencilParams P = shots[lo];
+        if (parity) {
+            float *c = const_cast<float *>(P.cur);
+            P.cur = P.nxt;
+            P.nxt = c;
+        }
+        const_tile<R, NDIM, TX, NW, MODE_FWD, NT>(P, t - tile_start[lo]);
+        __syncthreads();                      // LDS is reused by the next tile
+    }
+}
+
+// Tile shapes (rows, waves) instantiated for 3D grids; 2D grids use (1, 1).
+#define SW_CONST_SHAPES(X) X(16, 4) X(8, 4) X(32, 8) X(16, 8)
+
+template <int R, int NDIM, int TX, int NW, int NT>
+hipError_t launch_const_shape(int mode, StencilParams &P, hipStream_t s)
+{
+    const dim3 grid(P.ntx * P.nty * P.nzc), block(64 * NW);
+    switch (mode) {
+    case MODE_FWD: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_FWD, NT>), grid, block, 0, s, P); break;
+    case MODE_STORE: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_STORE, NT>), grid, block, 0, s, P); break;
+    default: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_IMAGE, NT>), grid, block, 0, s, P); break;
+    }
+    return hipGetLastError();
+}
+
+template <int R, int NT>
+hipError_t launch_const_nt(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
+{
+    if (ndim == 2) return launch_const_shape<R, 2, 1, 1, NT>(mode, P, s);
+#define SW_X(TXV, NWV) \
+    if (t.tx == TXV && t.nw == NWV) return launch_const_shape<R, 3, TXV, NWV, NT>(mode, P, s);
+    SW_CONST_SHAPES(SW_X)
+#undef SW_X
+    return hipErrorInvalidValue;
+}
+
+template <int R>
+hipError_t launch_const_radius(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
+{
+    return t.nt ? launch_const_nt<R, 1>(ndim, mode, t, P, s) : launch_const_nt<R, 0>(ndim, mode, t, P, s);
+}
+
+template <int R, int NT>
+hipError_t launch_batch_nt(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
+                           int nshots, int parity, int nblocks, hipStream_t s)
+{
+    if (ndim == 2) {
+        hipLaunchKernelGGL((k_const_batch<R, 2, 1, 1, NT>), dim3(nblocks), dim3(64), 0, s, shots, tile_start,
+                           nshots, parity);
+        return hipGetLastError();
+    }
+#define SW_X(TXV, NWV)                                                                            \
+    if (t.tx == TXV && t.nw == NWV) {                                                             \
+        hipLaunchKernelGGL((k_const_batch<R, 3, TXV, NWV, NT>), dim3(nblocks), dim3(64 * NWV), 0, s, \
+                           shots, tile_start, nshots, parity);                                    \
+        return hipGetLastError();                                                                 \
+    }
+    SW_CONST_SHAPES(SW_X)
+#undef SW_X
+    return hipErrorInvalidValue;
+}
+
+template <int R>
+hipError_t launch_batch_radius(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
+                               int nshots, int parity, int nblocks, hipStream_t s)
+{
+    return t.nt ? launch_batch_nt<R, 1>(ndim, t, shots, tile_start, nshots, parity, nblocks, s)
+                : launch_batch_nt<R, 0>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+}
+
+}  // namespace sw

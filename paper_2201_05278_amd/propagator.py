@@ -120,11 +120,12 @@ class Propagator:
     def grid_view(self, buf):
         """Extended-grid view of a padded-layout buffer (no copy)."""
         lay = self.layout
+        off = buf.storage_offset() + lay.origin
         if self.ndim == 3:
             p1, p2 = lay.padded[1], lay.padded[2]
-            return buf.as_strided(tuple(lay.dims[:3]), (p1 * p2, p2, 1), lay.origin)
+            return buf.as_strided(tuple(lay.dims[:3]), (p1 * p2, p2, 1), off)
         p1 = lay.padded[1]
-        return buf.as_strided(tuple(lay.dims[:2]), (p1, 1), lay.origin)
+        return buf.as_strided(tuple(lay.dims[:2]), (p1, 1), off)
 
     def physical_view(self, grid):
         """Physical part of an extended-grid array (paper: remove_nbl)."""
@@ -181,6 +182,30 @@ class Propagator:
         self._vel = vel
         self._rho = rho
         return self
+
+    # ---- tiling -------------------------------------------------------------
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1):
+        """Stencil tile shape, z-chunk length and cache policy (0 / -1: default)."""
+        L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, tx, nw, zc, nt))
+
+    def autotune(self, cache_path=None):
+        """Time candidate tilings on scratch buffers and keep the fastest (or
+        reuse the choice cached in the JSON file cache_path)."""
+        fields = (self.new_field(), self.new_field())
+        io = L.FwdIO()
+        io.workspace = _ptr(self.workspace).value
+        io.field[0], io.field[1] = fields[0].data_ptr(), fields[1].data_ptr()
+        L.check("sw_plan_autotune", L.lib().sw_plan_autotune(
+            self._plan, ctypes.byref(io), cache_path.encode() if cache_path else None, _stream()))
+
+    def _fwd_io(self, wavelet, fields, traces):
+        lay = self.layout
+        io = L.FwdIO()
+        io.workspace = _ptr(self.workspace).value
+        io.wavelet = wavelet.data_ptr() if lay.nsrc else None
+        io.field[0], io.field[1] = fields[0].data_ptr(), fields[1].data_ptr()
+        io.traces = traces.data_ptr() if lay.nrec else None
+        return io
 
     # ---- propagation --------------------------------------------------------
     def forward(self, wavelet, saving_stride=0, checkpoint_every=0, use_graph=False, fields=None,
@@ -258,6 +283,61 @@ class Propagator:
         self._keep_adj = (work, segment, grad_m, residual, wavelet)
         L.check("sw_adjoint", L.lib().sw_adjoint(self._plan, ctypes.byref(io), _stream()))
         return grad_vel, src_adj, grad_m
+
+
+class Batch:
+    """Many prepared constant-density propagators (shots) advanced together:
+    one persistent stencil launch per step over the tiles of all shots, one
+    batched injection and one batched recording launch."""
+
+    def __init__(self, props):
+        self.props = list(props)
+        arr = (ctypes.c_void_p * len(self.props))(*[p._plan.value for p in self.props])
+        handle = ctypes.c_void_p()
+        L.check("sw_batch_create", L.lib().sw_batch_create(len(self.props), arr, ctypes.byref(handle)))
+        self._batch = handle
+        nbytes = ctypes.c_int64()
+        L.check("sw_batch_layout", L.lib().sw_batch_layout(self._batch, ctypes.byref(nbytes)))
+        dev = self.props[0].device
+        self.table = torch.empty(max(256, nbytes.value), dtype=torch.uint8, device=dev)
+        self.fields = [(p.new_field(), p.new_field()) for p in self.props]
+        self.traces = [torch.zeros((p.nsteps, max(0, p.layout.nrec)), dtype=torch.float32, device=dev)
+                       for p in self.props]
+
+    def __del__(self):
+        try:
+            if getattr(self, "_batch", None):
+                L.lib().sw_batch_destroy(self._batch)
+                self._batch = None
+        except Exception:
+            pass
+
+    def _io(self, wavelets, nsteps_run, use_graph):
+        self._wav = [w.to(p.device, torch.float32).reshape(p.nsteps, -1).contiguous()
+                     for p, w in zip(self.props, wavelets)]
+        shots = (L.FwdIO * len(self.props))()
+        for k, p in enumerate(self.props):
+            shots[k] = p._fwd_io(self._wav[k], self.fields[k], self.traces[k])
+        io = L.BatchIO()
+        io.shots = shots
+        io.table = self.table.data_ptr()
+        io.nsteps_run = int(nsteps_run)
+        io.use_graph = 1 if use_graph else 0
+        self._shots = shots
+        return io
+
+    def autotune(self, wavelets, cache_path=None):
+        io = self._io(wavelets, self.props[0].nsteps, False)
+        L.check("sw_batch_autotune", L.lib().sw_batch_autotune(
+            self._batch, ctypes.byref(io), cache_path.encode() if cache_path else None, _stream()))
+
+    def forward(self, wavelets, nsteps_run=None, use_graph=False):
+        """Run all shots; returns the list of trace tensors (one per shot)."""
+        n = self.props[0].nsteps if nsteps_run is None else nsteps_run
+        io = self._io(wavelets, n, use_graph)
+        L.check("sw_batch_forward", L.lib().sw_batch_forward(self._batch, ctypes.byref(io), _stream()))
+        self.current = n % 2
+        return self.traces
 
 
 class AcousticForward(torch.autograd.Function):
