@@ -13,10 +13,15 @@ the fused absorbing layer, source injection and receiver recording.
   vd_staggered     forward Gpts/s, variable density (Gardner density), staggered
   roofline         dominant kernel (constant-density stencil): algorithmic
                    bytes per launch / average launch time from HIP events
+  batch            64 shots on uneven grids (160..256 x 160..320 x 160..320 + layer,
+                   own layered models, 10-20 Hz), all advanced by one persistent
+                   stencil launch per step (autotuned tiles, HIP graph), against a
+                   loop of single-shot launches of the same shots on the same GPU
   cpu_baseline     FP64 oracle on the host cores, first few steps of the same
                    workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --profile-pass     (5 forward steps + a 1 GiB copy, for counters)
 """
 import argparse
 import json
@@ -76,6 +81,63 @@ def time_fwd_adjoint(prop, wavelet, every):
     return el
 
 
+def batch_leg(nsteps, cache):
+    """Batched shots against a loop of single-shot launches (same shots, same GPU)."""
+    import torch
+    import workloads
+    from paper_2201_05278_amd import Propagator, Batch, critical_dt, ricker
+    shots = workloads.batch_3d(nshots=64, nsteps=nsteps)
+    props, wavs, nodes = [], [], 0.0
+    for wl in shots:
+        dt = workloads.CFL_FRACTION * critical_dt(wl.h, wl.space_order, wl.cmax)
+        p = Propagator(wl.n, wl.h, wl.space_order, dt, nsteps, nbl=wl.nbl)
+        p.set_sources(wl.src)
+        p.set_receivers(wl.rec)
+        p.prepare(torch.from_numpy(wl.vel).cuda(), cmax=wl.cmax)
+        props.append(p)
+        wavs.append(ricker(wl.f_peak, dt, nsteps).reshape(-1, 1).cuda())
+        nodes += float(np.prod([k + 2 * wl.nbl for k in wl.n]))
+    batch = Batch(props)
+    batch.autotune(wavs, cache)
+    batch.forward(wavs, nsteps_run=min(10, nsteps), use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.forward(wavs, use_graph=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    del batch
+    torch.cuda.empty_cache()
+    for p, w in zip(props[:2], wavs[:2]):
+        p.forward(w, nsteps_run=min(10, nsteps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, w in zip(props, wavs):
+        p.forward(w)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    return {"shots": len(props), "steps": nsteps, "nodes_per_step": int(nodes),
+            "batched_gpts": round(nodes * nsteps / t_batch / 1e9, 3),
+            "single_loop_gpts": round(nodes * nsteps / t_loop / 1e9, 3),
+            "speedup": round(t_loop / t_batch, 3)}
+
+
+def profile_pass(args):
+    """A short run for hardware counters: 5 forward steps of the workload with
+    the default tiling, then a plain 1 GiB device copy of known size."""
+    import torch
+    import workloads
+    from paper_2201_05278_amd import critical_dt, ricker
+    wl = workloads.smooth_3d(n=args.n, nsteps=6, scheme="vd_staggered")
+    dt = workloads.CFL_FRACTION * critical_dt(wl.h, wl.space_order, wl.cmax)
+    prop = make_prop(wl, "const", 6, dt)
+    prop.forward(ricker(wl.f_peak, dt, 6).reshape(-1, 1).cuda(), nsteps_run=5)
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("profile pass done: 5 steps of the 592^3 forward, 1 GiB copy", flush=True)
+
+
 def cpu_baseline(wl, dt, steps):
     """FP64 oracle, constant density, first `steps` steps of the workload."""
     import oracle
@@ -103,10 +165,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--ckpt-every", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-vd", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--tune-cache", default=os.path.join("/tmp", "simwave_tune.json"))
+    ap.add_argument("--profile-pass", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -118,6 +184,9 @@ def main():
     from paper_2201_05278_amd import critical_dt, ricker
 
     torch.cuda.set_device(0)
+    if args.profile_pass:
+        profile_pass(args)
+        return
     K, W = args.steps, args.warmup
     log(f"bench: building the smooth_3d model, n = {args.n}")
     wl = workloads.smooth_3d(n=args.n, nsteps=K + W, scheme="vd_staggered")
@@ -150,6 +219,13 @@ def main():
     log(f"bench: fwd+adjoint {fa:.1f} Gpts/s")
     del propa
     torch.cuda.empty_cache()
+
+    batch = None
+    if not args.skip_batch:
+        log(f"bench: 64 batched shots, {args.batch_steps} steps")
+        batch = batch_leg(args.batch_steps, args.tune_cache)
+        log(f"bench: batch {batch}")
+        torch.cuda.empty_cache()
 
     vd = None
     if not args.skip_vd:
@@ -191,6 +267,7 @@ def main():
         "pct_hbm_peak_forward": round(100.0 * gpts * BYTES_PER_NODE["const"] / HBM_PEAK_GBS, 2),
         "pct_hbm_peak_fwd_adjoint": round(100.0 * fa * 64 / HBM_PEAK_GBS, 2),
         "pct_hbm_peak_vd": None if vd is None else round(100.0 * vd * 20 / HBM_PEAK_GBS, 2),
+        "batch": batch,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "constant-density stencil, 16 B/node x nodes per launch",

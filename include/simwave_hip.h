@@ -240,12 +240,13 @@ typedef struct sw_adj_io {
 sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
 
 /* Override the stencil tiling of a plan: rows per tile `tx` and waves per
- * block `nw` (constant density in 3D: (16,4), (8,4), (32,8) or (16,8); other
- * schemes and 2D grids take 0, 0 for their fixed shape), z-chunk length `zc`
- * (0: default) and `nt` (1: non-temporal loads and stores for the streamed
- * arrays).  Results do not depend on the tiling.  tx = nw = zc = 0 and nt = -1
- * restores the defaults. */
-sw_status sw_plan_set_tiling(sw_plan *plan, int32_t tx, int32_t nw, int32_t zc, int32_t nt);
+ * block `nw` (constant density in 3D: (16,4), (8,4), (32,8), (16,8) or (8,8);
+ * other schemes and 2D grids take 0, 0 for their fixed shape), z-chunk length
+ * `zc` (0: default), `nt` (1: non-temporal loads and stores for the streamed
+ * arrays, 0: cached, -1: default) and `pf` (planes of loads in flight ahead
+ * of the update, 1 or 2; 0: default).  Results do not depend on the tiling. */
+sw_status sw_plan_set_tiling(sw_plan *plan, int32_t tx, int32_t nw, int32_t zc, int32_t nt,
+                             int32_t pf);
 
 /* ---- batched shots and autotuning --------------------------------------- */
 

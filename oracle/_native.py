@@ -54,5 +54,8 @@ def lib():
         L.ow_step.restype = None
         L.ow_apply_L.argtypes = [gp, ctypes.c_int32, dp, dp, dp]
         L.ow_apply_L.restype = None
+        ip = ctypes.POINTER(ctypes.c_int64)
+        L.ow_step_points.argtypes = [gp, ctypes.c_int32, dp, dp, dp, dp, dp, dp, ip, ctypes.c_int64, dp]
+        L.ow_step_points.restype = None
         _lib = L
     return _lib

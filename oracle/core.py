@@ -182,6 +182,27 @@ def step(st, p, prev, lap_out=None):
                   _ptr(st.K), _ptr(st.A), _ptr(st.B), _ptr(st.aux), _ptr(lap_out))
 
 
+def step_points(st, p, prev, idx):
+    """p^{n+1} (before injection) at the flat extended-grid indices idx, from
+    p^n = p and p^{n-1} = prev, without touching either."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx))
+    lib().ow_step_points(ctypes.byref(st.grid), SCHEMES[st.prob.scheme], _ptr(p), _ptr(prev),
+                         _ptr(st.K), _ptr(st.A), _ptr(st.B), _ptr(st.aux),
+                         idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(idx), _ptr(out))
+    return out
+
+
+def injection_terms(st, table, amplitudes):
+    """(nodes, values): what inject() adds at each node of a source table."""
+    nodes, ids, w = table
+    vals = st.A.ravel()[nodes] * st.M.ravel()[nodes] * (w / st.prob.dV) * amplitudes[ids]
+    u, inv = np.unique(nodes, return_inverse=True)
+    acc = np.zeros(len(u))
+    np.add.at(acc, inv, vals)
+    return u, acc
+
+
 def apply_L(st, p):
     out = np.empty_like(p)
     lib().ow_apply_L(ctypes.byref(st.grid), SCHEMES[st.prob.scheme], _ptr(p), _ptr(st.aux),

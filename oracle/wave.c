@@ -205,6 +205,20 @@ static int on_dirichlet_side(const ow_grid *g, const int64_t k[3])
     return 0;
 }
 
+/* The updated value p^{n+1} at node idx from p^n (p) and p^{n-1} (prev). */
+static double update_at(const ow_grid *g, int32_t scheme, const double *p, const double *prev,
+                        const double *K, const double *A, const double *B, const double *aux,
+                        int64_t idx, double *lap)
+{
+    int64_t k[3];
+    unlin(g, idx, k);
+    double Lp = apply_L(g, scheme, p, aux, k);
+    if (lap) *lap = Lp;
+    double next = A[idx] * (2.0 * p[idx] + K[idx] * Lp) - B[idx] * prev[idx];
+    if (on_dirichlet_side(g, k)) next = 0.0;
+    return next;
+}
+
 /* One leapfrog step.  p holds p^n; prev holds p^{n-1} on entry and p^{n+1}
  * on return (each node reads only its own previous value, so the overwrite is
  * safe).  If lap_out is not NULL it receives (L p^n). */
@@ -215,12 +229,20 @@ void ow_step(const ow_grid *g, int32_t scheme, const double *p, double *prev,
     const int64_t n = nnodes(g);
 #pragma omp parallel for schedule(static)
     for (int64_t idx = 0; idx < n; ++idx) {
-        int64_t k[3];
-        unlin(g, idx, k);
-        double Lp = apply_L(g, scheme, p, aux, k);
-        if (lap_out) lap_out[idx] = Lp;
-        double next = A[idx] * (2.0 * p[idx] + K[idx] * Lp) - B[idx] * prev[idx];
-        if (on_dirichlet_side(g, k)) next = 0.0;
+        double lap;
+        double next = update_at(g, scheme, p, prev, K, A, B, aux, idx, &lap);
+        if (lap_out) lap_out[idx] = lap;
         prev[idx] = next;
     }
+}
+
+/* The same update evaluated only at the nodes idx[0..n-1] (out[s] receives
+ * p^{n+1} at idx[s]); p and prev are not modified. */
+void ow_step_points(const ow_grid *g, int32_t scheme, const double *p, const double *prev,
+                    const double *K, const double *A, const double *B, const double *aux,
+                    const int64_t *idx, int64_t n, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s)
+        out[s] = update_at(g, scheme, p, prev, K, A, B, aux, idx[s], 0);
 }

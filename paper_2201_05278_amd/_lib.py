@@ -87,7 +87,7 @@ SIGNATURES = {
     "sw_model_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "sw_forward": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), c_void_p]),
     "sw_adjoint": (c_int32, [c_void_p, ctypes.POINTER(AdjIO), c_void_p]),
-    "sw_plan_set_tiling": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
+    "sw_plan_set_tiling": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "sw_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "sw_batch_destroy": (c_int32, [c_void_p]),
     "sw_batch_layout": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),

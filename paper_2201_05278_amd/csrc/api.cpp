@@ -61,9 +61,14 @@ PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap
     return t;
 }
 
+// Defaults from the tiling sweep of the 592^3 SO8 forward on MI355X.
+constexpr int kDefaultNT = 1;
+constexpr int kDefaultPF = 1;
+
 bool const_shape_ok(int tx, int nw)
 {
-    return (tx == 16 && nw == 4) || (tx == 8 && nw == 4) || (tx == 32 && nw == 8) || (tx == 16 && nw == 8);
+    return (tx == 16 && nw == 4) || (tx == 8 && nw == 4) || (tx == 32 && nw == 8) || (tx == 16 && nw == 8) ||
+           (tx == 8 && nw == 8);
 }
 
 // z-chunk length giving about `want` blocks in total (at least 4R planes).
@@ -90,11 +95,14 @@ Tiling choose_tiling(const sw_plan *p)
         t.tx = p->tile_tx;
         t.nw = p->tile_nw;
     } else {
-        t.tx = (p->r <= 4) ? 16 : 8;
+        t.tx = 8;
         t.nw = 4;
     }
-    t.zc = p->tile_zc ? std::min(p->tile_zc, p->dims[0]) : default_zc(p, t.tx, p->ndim == 2 ? 1024 : 2560);
-    t.nt = p->tile_nt;
+    // z chunks of about 74 planes (fewer if the grid has few tiles per plane)
+    t.zc = p->tile_zc ? std::min(p->tile_zc, p->dims[0])
+                      : std::min(std::min(74, p->dims[0]), default_zc(p, t.tx, p->ndim == 2 ? 1024 : 4096));
+    t.nt = p->tile_nt < 0 ? kDefaultNT : p->tile_nt;
+    t.pf = p->tile_pf ? p->tile_pf : kDefaultPF;
     return t;
 }
 
@@ -264,11 +272,12 @@ sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
     return SW_OK;
 }
 
-sw_status sw_plan_set_tiling(sw_plan *p, int32_t tx, int32_t nw, int32_t zc, int32_t nt)
+sw_status sw_plan_set_tiling(sw_plan *p, int32_t tx, int32_t nw, int32_t zc, int32_t nt, int32_t pf)
 {
     set_error("");
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
     if (zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
+    if (pf < 0 || pf > 2) return fail(SW_ERR_ARG, "pf must be 0, 1 or 2");
     if (tx || nw) {
         if (p->ndim != 3 || p->prob.scheme != SW_CONST)
             return fail(SW_ERR_UNSUPPORTED, "this scheme / dimension has a fixed tile shape");
@@ -277,7 +286,8 @@ sw_status sw_plan_set_tiling(sw_plan *p, int32_t tx, int32_t nw, int32_t zc, int
     p->tile_tx = tx;
     p->tile_nw = nw;
     p->tile_zc = zc;
-    p->tile_nt = nt < 0 ? 0 : (nt ? 1 : 0);
+    p->tile_nt = nt < 0 ? -1 : (nt ? 1 : 0);
+    p->tile_pf = pf;
     if (p->graph_exec) {
         (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
         p->graph_exec = nullptr;
@@ -594,7 +604,9 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
             std::swap(acur, anxt);   // phi^m becomes the current level
         }
     }
-    SW_HIP(launch_fold_gradient(make_geom(p), io->grad_m, io->vel, p->prob.dt, io->grad_vel, s));
+    // the forward work buffers are free now and hold the fold's partial sums
+    SW_HIP(launch_fold_gradient(make_geom(p), io->grad_m, io->vel, p->prob.dt, io->grad_vel, io->field[0],
+                                io->field[1], s));
     return SW_OK;
 }
 

@@ -20,7 +20,7 @@ struct sw_batch {
     std::vector<sw_plan *> plans;
     int nshots = 0;
     int r = 4, ndim = 3, nsteps = 0;
-    Tiling tiling{16, 4, 64, 0};
+    Tiling tiling{16, 4, 64, 1, 1};
     int bpc = 0;                        // persistent blocks per CU (0: default)
     int ncu = 256;
     // host staging of the device table
@@ -239,7 +239,7 @@ sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out)
     b->r = p0->r;
     b->ndim = p0->ndim;
     b->nsteps = p0->prob.nsteps;
-    b->tiling = Tiling{p0->ndim == 2 ? 1 : 16, p0->ndim == 2 ? 1 : 4, 64, 0};
+    b->tiling = Tiling{p0->ndim == 2 ? 1 : 8, p0->ndim == 2 ? 1 : 4, 64, 1, 1};
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
@@ -334,25 +334,28 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     auto it = cache.find(key);
     if (it != cache.end()) {
         auto &v = it->second;
-        return sw_plan_set_tiling(p, v["tx"], v["nw"], v["zc"], v["nt"]);
+        return sw_plan_set_tiling(p, v["tx"], v["nw"], v["zc"], v["nt"], v["pf"]);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<std::pair<int, int>> shapes;
-    if (p->ndim == 3 && p->prob.scheme == SW_CONST) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}};
+    if (p->ndim == 3 && p->prob.scheme == SW_CONST) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}, {8, 8}};
     else shapes = {{0, 0}};
+    const bool const3 = p->prob.scheme == SW_CONST;
     hipEvent_t e0, e1;
     SW_HIP(hipEventCreate(&e0));
     SW_HIP(hipEventCreate(&e1));
     float best = std::numeric_limits<float>::max();
-    int bt[4] = {0, 0, 0, 0};
+    int bt[5] = {0, 0, 0, 1, 1};
     StencilParams P;
     fill_params(p, io->workspace, P);
     P.cur = io->field[0];
     P.nxt = io->field[1];
     for (auto sh : shapes)
         for (int zc : zc_candidates(p->dims[0], p->r))
-            for (int nt : {0, 1}) {
-                st = sw_plan_set_tiling(p, sh.first, sh.second, zc, nt);
+            for (int nt : {0, 1})
+                for (int pf : {1, 2}) {
+                if (!const3 && (nt || pf == 2)) continue;
+                st = sw_plan_set_tiling(p, sh.first, sh.second, zc, nt, pf);
                 if (st != SW_OK) continue;
                 for (int w = 0; w < 2; ++w) SW_HIP(stencil(p, MODE_FWD, P, s));
                 SW_HIP(hipEventRecord(e0, s));
@@ -363,14 +366,14 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
                 const float ms = elapsed(e0, e1) / reps;
                 if (ms < best) {
                     best = ms;
-                    bt[0] = sh.first; bt[1] = sh.second; bt[2] = zc; bt[3] = nt;
+                    bt[0] = sh.first; bt[1] = sh.second; bt[2] = zc; bt[3] = nt; bt[4] = pf;
                 }
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    st = sw_plan_set_tiling(p, bt[0], bt[1], bt[2], bt[3]);
+    st = sw_plan_set_tiling(p, bt[0], bt[1], bt[2], bt[3], bt[4]);
     if (st != SW_OK) return st;
-    cache[key] = {{"tx", bt[0]}, {"nw", bt[1]}, {"zc", bt[2]}, {"nt", bt[3]}};
+    cache[key] = {{"tx", bt[0]}, {"nw", bt[1]}, {"zc", bt[2]}, {"nt", bt[3]}, {"pf", bt[4]}};
     write_cache(cache_path, cache);
     return SW_OK;
 }
@@ -394,14 +397,14 @@ sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cach
     if (it != cache.end()) {
         auto &v = it->second;
         if (b->ndim == 2 || const_shape_ok(v["tx"], v["nw"])) {
-            b->tiling = Tiling{v["tx"], v["nw"], v["zc"], v["nt"]};
+            b->tiling = Tiling{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"] ? v["pf"] : 1};
             b->bpc = v["bpc"];
             return SW_OK;
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<std::pair<int, int>> shapes;
-    if (b->ndim == 3) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}};
+    if (b->ndim == 3) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}, {8, 8}};
     else shapes = {{1, 1}};
     hipEvent_t e0, e1;
     SW_HIP(hipEventCreate(&e0));
@@ -432,8 +435,9 @@ sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cach
     // tile shape, z chunk and cache policy at the default grid, then the grid size
     for (auto sh : shapes)
         for (int zc : zc_candidates(zmin, b->r))
-            for (int nt : {0, 1}) {
-                b->tiling = Tiling{sh.first, sh.second, zc, nt};
+            for (int nt : {0, 1})
+                for (int pf : {1, 2}) {
+                b->tiling = Tiling{sh.first, sh.second, zc, nt, pf};
                 b->bpc = 0;
                 float ms = 0.0f;
                 sw_status st = time_cfg(ms);
@@ -457,7 +461,7 @@ sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cach
     b->bpc = bbpc;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    cache[key] = {{"tx", bt.tx}, {"nw", bt.nw}, {"zc", bt.zc}, {"nt", bt.nt}, {"bpc", bbpc}};
+    cache[key] = {{"tx", bt.tx}, {"nw", bt.nw}, {"zc", bt.zc}, {"nt", bt.nt}, {"pf", bt.pf}, {"bpc", bbpc}};
     write_cache(cache_path, cache);
     return SW_OK;
 }

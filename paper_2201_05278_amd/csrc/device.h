@@ -57,6 +57,7 @@ struct Tiling {
     int nw;                 // waves per block
     int zc;                 // z-chunk length
     int nt;                 // 1: non-temporal loads/stores for the streamed arrays
+    int pf;                 // planes of loads kept in flight ahead of the update (1 or 2)
 };
 
 hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);
@@ -109,7 +110,9 @@ hipError_t launch_inject(const PointTableDev &t, float *field, float *store, con
                          hipStream_t s);
 hipError_t launch_record(const PointTableDev &t, const float *field, float *out, hipStream_t s);
 hipError_t launch_snapshot(const Geom &g, const float *field, float *out, hipStream_t s);
+// Fold dJ/dM from the extended grid onto the physical grid and scale by
+// 2 dt^2 c; tmp0 / tmp1 hold Z*X*ny and Z*nx*ny floats.
 hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float *vel, double dt,
-                                float *grad_vel, hipStream_t s);
+                                float *grad_vel, float *tmp0, float *tmp1, hipStream_t s);
 
 }  // namespace sw

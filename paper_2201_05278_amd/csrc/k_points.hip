@@ -173,33 +173,43 @@ __global__ void k_snapshot(Geom g, const float *__restrict__ f, float *__restric
     }
 }
 
-// dJ/dc on the physical grid: every extended-grid node copies its model from
-// one physical node, so the physical node gathers 2 dt^2 c dJ/dM over the
-// block of extended nodes that copy it (a single node away from the edges).
-__global__ void k_fold_gradient(Geom g, const float *__restrict__ gm, const float *__restrict__ vel,
-                                float two_dt2, float *__restrict__ gv)
+// dJ/dc on the physical grid.  Every extended-grid node copies its model from
+// the nearest physical node, so the transpose of that copy sums the layer
+// cells of each axis onto the physical edge cell.  The sum is separable and is
+// done one axis at a time (y, then x, then z), each pass summing at most
+// layer+1 inputs per output in a fixed order; `in` and `out` use dense
+// (z, x, y) arrays of the stated extents, except that pass 0 reads the padded
+// extended-grid layout.
+__global__ void k_fold_axis(Geom g, int pass, const float *__restrict__ in, float *__restrict__ out,
+                            const float *__restrict__ vel, float two_dt2)
 {
-    const int64_t total = int64_t(g.np[0]) * g.np[1] * g.np[2];
+    // extents of the input (iz, ix, iy) and output (oz, ox, oy) of this pass
+    const int iz = g.Z, ix = (pass == 0) ? g.X : (pass == 1 ? g.X : g.np[1]);
+    const int iy = (pass == 0) ? g.Y : g.np[2];
+    const int oz = (pass == 2) ? g.np[0] : g.Z;
+    const int ox = (pass >= 1) ? g.np[1] : g.X;
+    const int oy = g.np[2];
+    (void)iz;
+    const int64_t total = int64_t(oz) * ox * oy;
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * blockDim.x) {
-        const int py = int(i % g.np[2]);
-        const int64_t t = i / g.np[2];
-        const int px = int(t % g.np[1]);
-        const int pz = int(t / g.np[1]);
-        const int ext[3] = {g.Z, g.X, g.Y};
-        const int pc[3] = {pz, px, py};
-        int a[3], b[3];
-        for (int k = 0; k < 3; ++k) {
-            a[k] = pc[k] + g.lo[k];
-            b[k] = a[k];
-            if (pc[k] == 0) a[k] = 0;
-            if (pc[k] == g.np[k] - 1) b[k] = ext[k] - 1;
-        }
+        const int y = int(i % oy);
+        const int64_t t = i / oy;
+        const int x = int(t % ox);
+        const int z = int(t / ox);
+        const int ax = (pass == 0) ? 2 : (pass == 1 ? 1 : 0);      // axis folded in this pass
+        const int c = (ax == 2) ? y : (ax == 1 ? x : z);           // physical index on that axis
+        const int ext = (ax == 2) ? g.Y : (ax == 1 ? g.X : g.Z);
+        int a = c + g.lo[ax], b = a;
+        if (c == 0) a = 0;
+        if (c == g.np[ax] - 1) b = ext - 1;
         float s = 0.0f;
-        for (int z = a[0]; z <= b[0]; ++z)
-            for (int x = a[1]; x <= b[1]; ++x)
-                for (int y = a[2]; y <= b[2]; ++y) s += gm[elem(g, z, x, y)];
-        gv[i] = s * two_dt2 * vel[i];
+        for (int k = a; k <= b; ++k) {
+            if (pass == 0) s += in[elem(g, z, x, k)];
+            else if (pass == 1) s += in[(int64_t(z) * ix + k) * iy + y];
+            else s += in[(int64_t(k) * ix + x) * iy + y];
+        }
+        out[i] = (pass == 2) ? s * two_dt2 * vel[i] : s;
     }
 }
 
@@ -326,11 +336,15 @@ hipError_t launch_snapshot(const Geom &g, const float *field, float *out, hipStr
 }
 
 hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float *vel, double dt,
-                                float *grad_vel, hipStream_t s)
+                                float *grad_vel, float *tmp0, float *tmp1, hipStream_t s)
 {
-    const int64_t total = int64_t(g.np[0]) * g.np[1] * g.np[2];
-    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, grad_m,
-                       vel, float(2.0 * dt * dt), grad_vel);
+    const float two_dt2 = float(2.0 * dt * dt);
+    const int64_t n0 = int64_t(g.Z) * g.X * g.np[2];
+    const int64_t n1 = int64_t(g.Z) * g.np[1] * g.np[2];
+    const int64_t n2 = int64_t(g.np[0]) * g.np[1] * g.np[2];
+    hipLaunchKernelGGL(k_fold_axis, dim3(blocks_for(n0)), dim3(kBlock), 0, s, g, 0, grad_m, tmp0, vel, two_dt2);
+    hipLaunchKernelGGL(k_fold_axis, dim3(blocks_for(n1)), dim3(kBlock), 0, s, g, 1, tmp0, tmp1, vel, two_dt2);
+    hipLaunchKernelGGL(k_fold_axis, dim3(blocks_for(n2)), dim3(kBlock), 0, s, g, 2, tmp1, grad_vel, vel, two_dt2);
     return hipGetLastError();
 }
 

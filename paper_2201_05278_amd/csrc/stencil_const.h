@@ -45,7 +45,7 @@ __device__ __forceinline__ void st_stream(float v, float *p)
 
 // One tile (TX x 64 columns, one z chunk) of one grid; `bid` is the tile's
 // index in (z chunk, x tile, y tile) order.
-template <int R, int NDIM, int TX, int NW, int MODE, int NT>
+template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
 __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
 {
     static_assert(TX % NW == 0, "rows must split evenly over waves");
@@ -128,10 +128,12 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         for (int i = 0; i < RPT; ++i) q[i][k] = (rin[i] && zin) ? pl[ro[i]] : 0.0f;
     }
 
-    // registers filled one plane ahead
-    float nf[RPT], np_[RPT], nk[RPT], na[RPT], nb[RPT], nd[RPT], ng[RPT];
-    float nhx[HXN > 0 ? HXN : 1], nhy[YHN];
-    auto load = [&](int z) {
+    // loads for a plane, issued PF planes ahead of its use
+    struct Slot {
+        float f[RPT], p[RPT], k[RPT], a[RPT], b[RPT], d[RPT], g[RPT];
+        float hx[HXN > 0 ? HXN : 1], hy[YHN];
+    };
+    auto load = [&](int z, Slot &S) {
         const int zf = z + R;
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
         const float *pc = cur0 + int64_t(z) * sz;
@@ -141,61 +143,43 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         const bool fin = zf < g.Z;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            nf[i] = (rin[i] && fin) ? pf[ro[i]] : 0.0f;
-            np_[i] = rin[i] ? ld_stream<NT>(pn + ro[i]) : 0.0f;
-            nk[i] = rin[i] ? ld_stream<NT>(pk + ro[i]) : 0.0f;
+            S.f[i] = (rin[i] && fin) ? pf[ro[i]] : 0.0f;
+            S.p[i] = rin[i] ? ld_stream<NT>(pn + ro[i]) : 0.0f;
+            S.k[i] = rin[i] ? ld_stream<NT>(pk + ro[i]) : 0.0f;
             const int d2 = ez * ez + ex2[i];
-            na[i] = 1.0f;
-            nb[i] = 1.0f;
+            S.a[i] = 1.0f;
+            S.b[i] = 1.0f;
             if (rin[i] && d2 > 0) {
                 const float2 ab = P.damp[d2];
-                na[i] = ab.x;
-                nb[i] = ab.y;
+                S.a[i] = ab.x;
+                S.b[i] = ab.y;
             }
             if constexpr (MODE == MODE_IMAGE) {
                 const int64_t o = int64_t(z) * sz + g.base + ro[i];
-                nd[i] = rin[i] ? ld_stream<NT>(P.store + o) : 0.0f;
-                ng[i] = rin[i] ? ld_stream<NT>(P.grad + o) : 0.0f;
+                S.d[i] = rin[i] ? ld_stream<NT>(P.store + o) : 0.0f;
+                S.g[i] = rin[i] ? ld_stream<NT>(P.grad + o) : 0.0f;
             }
         }
 #pragma unroll
-        for (int s = 0; s < HXN; ++s) nhx[s] = hxin[s] ? pc[hxo[s]] : 0.0f;
+        for (int s = 0; s < HXN; ++s) S.hx[s] = hxin[s] ? pc[hxo[s]] : 0.0f;
 #pragma unroll
-        for (int s = 0; s < YHN; ++s) nhy[s] = hyin[s] ? pc[hyo[s]] : 0.0f;
+        for (int s = 0; s < YHN; ++s) S.hy[s] = hyin[s] ? pc[hyo[s]] : 0.0f;
     };
 
-    load(zb);
-    int buf = 0;
-    for (int z = zb; z < ze; ++z) {
-        float pp[RPT], pk[RPT], pa[RPT], pb[RPT], pd[RPT], pg[RPT];
-        float hx[HXN > 0 ? HXN : 1], hy[YHN];
+    // consume the slot of plane z (then refill it for plane z + PF) and update plane z
+    auto plane = [&](int z, Slot &S, float (*T)[LY]) {
+        const Slot W = S;
+        if (z + PF < ze) load(z + PF, S);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            q[i][2 * R] = nf[i];
-            pp[i] = np_[i];
-            pk[i] = nk[i];
-            pa[i] = na[i];
-            pb[i] = nb[i];
-            if constexpr (MODE == MODE_IMAGE) {
-                pd[i] = nd[i];
-                pg[i] = ng[i];
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < HXN; ++s) hx[s] = nhx[s];
-#pragma unroll
-        for (int s = 0; s < YHN; ++s) hy[s] = nhy[s];
-        if (z + 1 < ze) load(z + 1);
-
-        float(*T)[LY] = lds[buf];
+        for (int i = 0; i < RPT; ++i) q[i][2 * R] = W.f[i];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) T[HXR + wave * RPT + i][R + lane] = q[i][R];
 #pragma unroll
         for (int s = 0; s < HXN; ++s)
-            if (hxok[s]) T[hxrow[s]][R + lane] = hx[s];
+            if (hxok[s]) T[hxrow[s]][R + lane] = W.hx[s];
 #pragma unroll
         for (int s = 0; s < YHN; ++s)
-            if (hyok[s]) T[hyrow[s]][hycol[s]] = hy[s];
+            if (hyok[s]) T[hyrow[s]][hycol[s]] = W.hy[s];
         __syncthreads();
 
         float *pn = nxt0 + int64_t(z) * sz;
@@ -212,27 +196,42 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
             }
 #pragma unroll
             for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[lx][ly + j] + T[lx][ly - j], lap);
-            const float out = pa[i] * fmaf(pk[i], lap, 2.0f * c) - pb[i] * pp[i];
+            const float out = W.a[i] * fmaf(W.k[i], lap, 2.0f * c) - W.b[i] * W.p[i];
             if (rin[i]) {
                 st_stream<NT>(out, pn + ro[i]);
                 const int64_t o = int64_t(z) * sz + g.base + ro[i];
-                if constexpr (MODE == MODE_STORE) st_stream<NT>(pk[i] * lap, P.store + o);
+                if constexpr (MODE == MODE_STORE) st_stream<NT>(W.k[i] * lap, P.store + o);
                 if constexpr (MODE == MODE_IMAGE)
-                    st_stream<NT>(fmaf(c, pd[i] / (pk[i] * pk[i]), pg[i]), P.grad + o);
+                    st_stream<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), P.grad + o);
             }
         }
-        buf ^= 1;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int k = 0; k < 2 * R; ++k) q[i][k] = q[i][k + 1];
+    };
+
+    Slot s0, s1;
+    load(zb, s0);
+    if constexpr (PF == 2) {
+        if (zb + 1 < ze) load(zb + 1, s1);
+        for (int z = zb; z < ze; z += 2) {
+            plane(z, s0, lds[0]);
+            if (z + 1 < ze) plane(z + 1, s1, lds[1]);
+        }
+    } else {
+        int buf = 0;
+        for (int z = zb; z < ze; ++z) {
+            plane(z, s0, lds[buf]);
+            buf ^= 1;
+        }
     }
 }
 
-template <int R, int NDIM, int TX, int NW, int MODE, int NT>
+template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
 __global__ void __launch_bounds__(64 * NW) k_const(StencilParams P)
 {
-    const_tile<R, NDIM, TX, NW, MODE, NT>(P, xcd_remap(blockIdx.x, gridDim.x));
+    const_tile<R, NDIM, TX, NW, MODE, NT, PF>(P, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Many grids (shots) in one persistent launch: the tiles of all shots form
@@ -240,7 +239,7 @@ __global__ void __launch_bounds__(64 * NW) k_const(StencilParams P)
 // tiles blockIdx, blockIdx + gridDim, ... (XCD-aware), looks up the shot and
 // runs the same tile code on that shot's arrays.  `parity` swaps the two
 // wavefield buffers of every shot.
-template <int R, int NDIM, int TX, int NW, int NT>
+template <int R, int NDIM, int TX, int NW, int NT, int PF>
 __global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__restrict__ shots,
                                                          const int *__restrict__ tile_start,
                                                          int nshots, int parity)
@@ -259,32 +258,32 @@ __global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__
             P.cur = P.nxt;
             P.nxt = c;
         }
-        const_tile<R, NDIM, TX, NW, MODE_FWD, NT>(P, t - tile_start[lo]);
+        const_tile<R, NDIM, TX, NW, MODE_FWD, NT, PF>(P, t - tile_start[lo]);
         __syncthreads();                      // LDS is reused by the next tile
     }
 }
 
 // Tile shapes (rows, waves) instantiated for 3D grids; 2D grids use (1, 1).
-#define SW_CONST_SHAPES(X) X(16, 4) X(8, 4) X(32, 8) X(16, 8)
+#define SW_CONST_SHAPES(X) X(16, 4) X(8, 4) X(32, 8) X(16, 8) X(8, 8)
 
-template <int R, int NDIM, int TX, int NW, int NT>
+template <int R, int NDIM, int TX, int NW, int NT, int PF>
 hipError_t launch_const_shape(int mode, StencilParams &P, hipStream_t s)
 {
     const dim3 grid(P.ntx * P.nty * P.nzc), block(64 * NW);
     switch (mode) {
-    case MODE_FWD: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_FWD, NT>), grid, block, 0, s, P); break;
-    case MODE_STORE: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_STORE, NT>), grid, block, 0, s, P); break;
-    default: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_IMAGE, NT>), grid, block, 0, s, P); break;
+    case MODE_FWD: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_FWD, NT, PF>), grid, block, 0, s, P); break;
+    case MODE_STORE: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_STORE, NT, PF>), grid, block, 0, s, P); break;
+    default: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_IMAGE, NT, PF>), grid, block, 0, s, P); break;
     }
     return hipGetLastError();
 }
 
-template <int R, int NT>
-hipError_t launch_const_nt(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
+template <int R, int NT, int PF>
+hipError_t launch_const_v(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    if (ndim == 2) return launch_const_shape<R, 2, 1, 1, NT>(mode, P, s);
+    if (ndim == 2) return launch_const_shape<R, 2, 1, 1, NT, PF>(mode, P, s);
 #define SW_X(TXV, NWV) \
-    if (t.tx == TXV && t.nw == NWV) return launch_const_shape<R, 3, TXV, NWV, NT>(mode, P, s);
+    if (t.tx == TXV && t.nw == NWV) return launch_const_shape<R, 3, TXV, NWV, NT, PF>(mode, P, s);
     SW_CONST_SHAPES(SW_X)
 #undef SW_X
     return hipErrorInvalidValue;
@@ -293,23 +292,25 @@ hipError_t launch_const_nt(int ndim, int mode, const Tiling &t, StencilParams &P
 template <int R>
 hipError_t launch_const_radius(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    return t.nt ? launch_const_nt<R, 1>(ndim, mode, t, P, s) : launch_const_nt<R, 0>(ndim, mode, t, P, s);
+    if (t.pf == 2)
+        return t.nt ? launch_const_v<R, 1, 2>(ndim, mode, t, P, s) : launch_const_v<R, 0, 2>(ndim, mode, t, P, s);
+    return t.nt ? launch_const_v<R, 1, 1>(ndim, mode, t, P, s) : launch_const_v<R, 0, 1>(ndim, mode, t, P, s);
 }
 
-template <int R, int NT>
-hipError_t launch_batch_nt(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
-                           int nshots, int parity, int nblocks, hipStream_t s)
+template <int R, int NT, int PF>
+hipError_t launch_batch_v(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
+                          int nshots, int parity, int nblocks, hipStream_t s)
 {
     if (ndim == 2) {
-        hipLaunchKernelGGL((k_const_batch<R, 2, 1, 1, NT>), dim3(nblocks), dim3(64), 0, s, shots, tile_start,
-                           nshots, parity);
+        hipLaunchKernelGGL((k_const_batch<R, 2, 1, 1, NT, PF>), dim3(nblocks), dim3(64), 0, s, shots,
+                           tile_start, nshots, parity);
         return hipGetLastError();
     }
-#define SW_X(TXV, NWV)                                                                            \
-    if (t.tx == TXV && t.nw == NWV) {                                                             \
-        hipLaunchKernelGGL((k_const_batch<R, 3, TXV, NWV, NT>), dim3(nblocks), dim3(64 * NWV), 0, s, \
-                           shots, tile_start, nshots, parity);                                    \
-        return hipGetLastError();                                                                 \
+#define SW_X(TXV, NWV)                                                                               \
+    if (t.tx == TXV && t.nw == NWV) {                                                                \
+        hipLaunchKernelGGL((k_const_batch<R, 3, TXV, NWV, NT, PF>), dim3(nblocks), dim3(64 * NWV), 0, s, \
+                           shots, tile_start, nshots, parity);                                       \
+        return hipGetLastError();                                                                    \
     }
     SW_CONST_SHAPES(SW_X)
 #undef SW_X
@@ -320,8 +321,11 @@ template <int R>
 hipError_t launch_batch_radius(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
                                int nshots, int parity, int nblocks, hipStream_t s)
 {
-    return t.nt ? launch_batch_nt<R, 1>(ndim, t, shots, tile_start, nshots, parity, nblocks, s)
-                : launch_batch_nt<R, 0>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+    if (t.pf == 2)
+        return t.nt ? launch_batch_v<R, 1, 2>(ndim, t, shots, tile_start, nshots, parity, nblocks, s)
+                    : launch_batch_v<R, 0, 2>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+    return t.nt ? launch_batch_v<R, 1, 1>(ndim, t, shots, tile_start, nshots, parity, nblocks, s)
+                : launch_batch_v<R, 0, 1>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
 }
 
 }  // namespace sw

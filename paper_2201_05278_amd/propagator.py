@@ -184,9 +184,10 @@ class Propagator:
         return self
 
     # ---- tiling -------------------------------------------------------------
-    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1):
-        """Stencil tile shape, z-chunk length and cache policy (0 / -1: default)."""
-        L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, tx, nw, zc, nt))
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0):
+        """Stencil tile shape, z-chunk length, cache policy and prefetch
+        distance (0 / -1: default)."""
+        L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, tx, nw, zc, nt, pf))
 
     def autotune(self, cache_path=None):
         """Time candidate tilings on scratch buffers and keep the fastest (or
