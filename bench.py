@@ -39,6 +39,14 @@ BYTES_PER_NODE = {"const": 16, "vd_staggered": 20, "vd_centred": 20}
 METRIC = "Gpts/s (grid updates/s) fwd and fwd+adjoint, 3D 512^3 SO8 FP32; % HBM peak"
 
 
+# HBM bytes per launch of the dominant kernel from the counter runs recorded in
+# profiles/stencil_const_smooth3d_592_traffic.md (FETCH_SIZE x 2.000 and
+# WRITE_SIZE x 1.000, both calibrated on a 1 GiB copy), valid only for the
+# kernel configuration that was profiled.
+PROFILED = {"tiling": {"tx": 8, "nw": 4, "zc": 74, "nt": 1, "pf": 1, "wt": 0},
+            "n": 512, "bytes": (1431548.5 * 2.000 + 810448.0 * 1.000) * 1024}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -204,6 +212,8 @@ def main():
     achieved = nodes * BYTES_PER_NODE["const"] / (avg_ms * 1e-3) / 1e9
     out["forward"] = gpts
     out["stencil_ms"] = avg_ms
+    tiling = prop.tiling
+    traffic = PROFILED["bytes"] if (tiling == PROFILED["tiling"] and args.n == PROFILED["n"]) else None
     log(f"bench: forward {gpts:.1f} Gpts/s, stencil {avg_ms:.3f} ms -> {achieved:.0f} GB/s")
     del prop
     torch.cuda.empty_cache()
@@ -269,7 +279,9 @@ def main():
         "pct_hbm_peak_vd": None if vd is None else round(100.0 * vd * 20 / HBM_PEAK_GBS, 2),
         "batch": batch,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "traffic_unit": "GB per launch", "tiling": tiling,
                      "kernel": "constant-density stencil, 16 B/node x nodes per launch",
                      "avg_launch_ms": round(avg_ms, 4)},
         "cpu_baseline": cpu,

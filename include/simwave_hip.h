@@ -239,14 +239,26 @@ typedef struct sw_adj_io {
  * summed back from the layer onto the physical node it copies. */
 sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
 
-/* Override the stencil tiling of a plan: rows per tile `tx` and waves per
- * block `nw` (constant density in 3D: (16,4), (8,4), (32,8), (16,8) or (8,8);
- * other schemes and 2D grids take 0, 0 for their fixed shape), z-chunk length
- * `zc` (0: default), `nt` (1: non-temporal loads and stores for the streamed
- * arrays, 0: cached, -1: default) and `pf` (planes of loads in flight ahead
- * of the update, 1 or 2; 0: default).  Results do not depend on the tiling. */
-sw_status sw_plan_set_tiling(sw_plan *plan, int32_t tx, int32_t nw, int32_t zc, int32_t nt,
-                             int32_t pf);
+/* Stencil tiling of a plan.  Results never depend on it.
+ *   tx, nw  rows per block and waves per block.  3D constant density:
+ *           block tiles (16,4), (8,4), (32,8), (16,8), (8,8), or with wt = 1
+ *           wave tiles (16,4), (32,4), (4,1), (8,1), (16,2) (each wave owns
+ *           tx / nw rows); 3D variable density: (16,8), (8,8), (8,4), (16,4);
+ *           2D grids: fixed.  0, 0: default.
+ *   zc      z-chunk length (0: default)
+ *   nt      1: non-temporal loads/stores for the streamed arrays, 0: cached,
+ *           -1: default
+ *   pf      planes of loads in flight ahead of the update (1 or 2; 0: default;
+ *           block tiles only)
+ *   wt      1: wave tiles (see tx, nw) */
+typedef struct sw_tiling {
+    int32_t tx, nw, zc, nt, pf, wt;
+} sw_tiling;
+
+/* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan. */
+sw_status sw_plan_set_tiling(sw_plan *plan, const sw_tiling *t);
+/* The tiling the plan's stencil launches use (defaults resolved). */
+sw_status sw_plan_get_tiling(const sw_plan *plan, sw_tiling *out);
 
 /* ---- batched shots and autotuning --------------------------------------- */
 

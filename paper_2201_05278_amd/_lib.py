@@ -63,6 +63,11 @@ class AdjIO(ctypes.Structure):
                 ("grad_m", c_void_p), ("grad_vel", c_void_p), ("src_adjoint", c_void_p)]
 
 
+class Tiling(ctypes.Structure):
+    _fields_ = [("tx", c_int32), ("nw", c_int32), ("zc", c_int32), ("nt", c_int32), ("pf", c_int32),
+                ("wt", c_int32)]
+
+
 class BatchIO(ctypes.Structure):
     _fields_ = [("shots", ctypes.POINTER(FwdIO)), ("table", c_void_p), ("nsteps_run", c_int32),
                 ("use_graph", c_int32)]
@@ -87,7 +92,8 @@ SIGNATURES = {
     "sw_model_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "sw_forward": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), c_void_p]),
     "sw_adjoint": (c_int32, [c_void_p, ctypes.POINTER(AdjIO), c_void_p]),
-    "sw_plan_set_tiling": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "sw_plan_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
+    "sw_plan_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
     "sw_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "sw_batch_destroy": (c_int32, [c_void_p]),
     "sw_batch_layout": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),

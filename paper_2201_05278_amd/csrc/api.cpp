@@ -71,6 +71,17 @@ bool const_shape_ok(int tx, int nw)
            (tx == 8 && nw == 8);
 }
 
+bool wave_shape_ok(int tx, int nw)
+{
+    return (tx == 16 && nw == 4) || (tx == 32 && nw == 4) || (tx == 4 && nw == 1) || (tx == 8 && nw == 1) ||
+           (tx == 16 && nw == 2);
+}
+
+bool vd_shape_ok(int tx, int nw)
+{
+    return (tx == 16 && nw == 8) || (tx == 8 && nw == 8) || (tx == 8 && nw == 4) || (tx == 16 && nw == 4);
+}
+
 // z-chunk length giving about `want` blocks in total (at least 4R planes).
 int default_zc(const sw_plan *p, int tx, int64_t want)
 {
@@ -89,11 +100,14 @@ Tiling choose_tiling(const sw_plan *p)
         t.tx = 1;
         t.nw = 1;
     } else if (p->prob.scheme != SW_CONST) {
-        t.tx = 16;      // variable-density kernels: 16 rows, 8 waves
-        t.nw = 8;
+        // variable-density kernels: 8x8 staggered, 16x8 centred (tiling sweep, 592^3 SO8)
+        const int dtx = p->prob.scheme == SW_VD_STAGGERED ? 8 : 16;
+        t.tx = p->tile_tx ? p->tile_tx : dtx;
+        t.nw = p->tile_tx ? p->tile_nw : 8;
     } else if (p->tile_tx) {
         t.tx = p->tile_tx;
         t.nw = p->tile_nw;
+        t.wt = p->tile_wt;
     } else {
         t.tx = 8;
         t.nw = 4;
@@ -272,26 +286,42 @@ sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
     return SW_OK;
 }
 
-sw_status sw_plan_set_tiling(sw_plan *p, int32_t tx, int32_t nw, int32_t zc, int32_t nt, int32_t pf)
+sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
 {
     set_error("");
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
-    if (zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
-    if (pf < 0 || pf > 2) return fail(SW_ERR_ARG, "pf must be 0, 1 or 2");
-    if (tx || nw) {
-        if (p->ndim != 3 || p->prob.scheme != SW_CONST)
-            return fail(SW_ERR_UNSUPPORTED, "this scheme / dimension has a fixed tile shape");
-        if (!const_shape_ok(tx, nw)) return fail(SW_ERR_UNSUPPORTED, "tile shape not provided");
+    sw_tiling d{0, 0, 0, -1, 0, 0};
+    if (t) d = *t;
+    if (d.zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
+    if (d.pf < 0 || d.pf > 2) return fail(SW_ERR_ARG, "pf must be 0, 1 or 2");
+    if (d.wt && p->prob.scheme != SW_CONST) return fail(SW_ERR_UNSUPPORTED, "wave tiles cover constant density");
+    if (d.tx || d.nw) {
+        if (p->ndim != 3) return fail(SW_ERR_UNSUPPORTED, "2D grids have a fixed tile shape");
+        const bool ok = p->prob.scheme != SW_CONST ? vd_shape_ok(d.tx, d.nw)
+                        : (d.wt ? wave_shape_ok(d.tx, d.nw) : const_shape_ok(d.tx, d.nw));
+        if (!ok) return fail(SW_ERR_UNSUPPORTED, "tile shape not provided");
+    } else if (d.wt) {
+        return fail(SW_ERR_ARG, "wave tiles need an explicit shape");
     }
-    p->tile_tx = tx;
-    p->tile_nw = nw;
-    p->tile_zc = zc;
-    p->tile_nt = nt < 0 ? -1 : (nt ? 1 : 0);
-    p->tile_pf = pf;
+    p->tile_tx = d.tx;
+    p->tile_nw = d.nw;
+    p->tile_zc = d.zc;
+    p->tile_nt = d.nt < 0 ? -1 : (d.nt ? 1 : 0);
+    p->tile_pf = d.pf;
+    p->tile_wt = d.wt ? 1 : 0;
     if (p->graph_exec) {
         (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
         p->graph_exec = nullptr;
     }
+    return SW_OK;
+}
+
+sw_status sw_plan_get_tiling(const sw_plan *p, sw_tiling *out)
+{
+    set_error("");
+    if (!p || !out) return fail(SW_ERR_ARG, "NULL argument");
+    const Tiling t = choose_tiling(p);
+    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt};
     return SW_OK;
 }
 

@@ -20,7 +20,7 @@ struct sw_batch {
     std::vector<sw_plan *> plans;
     int nshots = 0;
     int r = 4, ndim = 3, nsteps = 0;
-    Tiling tiling{16, 4, 64, 1, 1};
+    Tiling tiling{16, 4, 64, 1, 1, 0};
     int bpc = 0;                        // persistent blocks per CU (0: default)
     int ncu = 256;
     // host staging of the device table
@@ -239,7 +239,7 @@ sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out)
     b->r = p0->r;
     b->ndim = p0->ndim;
     b->nsteps = p0->prob.nsteps;
-    b->tiling = Tiling{p0->ndim == 2 ? 1 : 8, p0->ndim == 2 ? 1 : 4, 64, 1, 1};
+    b->tiling = Tiling{p0->ndim == 2 ? 1 : 8, p0->ndim == 2 ? 1 : 4, 64, 1, 1, 0};
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
@@ -334,18 +334,25 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     auto it = cache.find(key);
     if (it != cache.end()) {
         auto &v = it->second;
-        return sw_plan_set_tiling(p, v["tx"], v["nw"], v["zc"], v["nt"], v["pf"]);
+        const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"]};
+        return sw_plan_set_tiling(p, &t);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<std::pair<int, int>> shapes;
-    if (p->ndim == 3 && p->prob.scheme == SW_CONST) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}, {8, 8}};
-    else shapes = {{0, 0}};
+    struct Shape { int tx, nw, wt; };
+    std::vector<Shape> shapes;
+    if (p->ndim == 3 && p->prob.scheme == SW_CONST)
+        shapes = {{16, 4, 0}, {8, 4, 0}, {32, 8, 0}, {16, 8, 0}, {8, 8, 0},
+                  {16, 4, 1}, {32, 4, 1}, {4, 1, 1}, {8, 1, 1}, {16, 2, 1}};
+    else if (p->ndim == 3)
+        shapes = {{16, 8, 0}, {8, 8, 0}, {8, 4, 0}, {16, 4, 0}};
+    else
+        shapes = {{0, 0, 0}};
     const bool const3 = p->prob.scheme == SW_CONST;
     hipEvent_t e0, e1;
     SW_HIP(hipEventCreate(&e0));
     SW_HIP(hipEventCreate(&e1));
     float best = std::numeric_limits<float>::max();
-    int bt[5] = {0, 0, 0, 1, 1};
+    sw_tiling best_t{0, 0, 0, -1, 0, 0};
     StencilParams P;
     fill_params(p, io->workspace, P);
     P.cur = io->field[0];
@@ -354,8 +361,9 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
         for (int zc : zc_candidates(p->dims[0], p->r))
             for (int nt : {0, 1})
                 for (int pf : {1, 2}) {
-                if (!const3 && (nt || pf == 2)) continue;
-                st = sw_plan_set_tiling(p, sh.first, sh.second, zc, nt, pf);
+                if ((!const3 || sh.wt) && pf == 2) continue;
+                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt};
+                st = sw_plan_set_tiling(p, &cand);
                 if (st != SW_OK) continue;
                 for (int w = 0; w < 2; ++w) SW_HIP(stencil(p, MODE_FWD, P, s));
                 SW_HIP(hipEventRecord(e0, s));
@@ -366,14 +374,15 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
                 const float ms = elapsed(e0, e1) / reps;
                 if (ms < best) {
                     best = ms;
-                    bt[0] = sh.first; bt[1] = sh.second; bt[2] = zc; bt[3] = nt; bt[4] = pf;
+                    best_t = cand;
                 }
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    st = sw_plan_set_tiling(p, bt[0], bt[1], bt[2], bt[3], bt[4]);
+    st = sw_plan_set_tiling(p, &best_t);
     if (st != SW_OK) return st;
-    cache[key] = {{"tx", bt[0]}, {"nw", bt[1]}, {"zc", bt[2]}, {"nt", bt[3]}, {"pf", bt[4]}};
+    cache[key] = {{"tx", best_t.tx}, {"nw", best_t.nw}, {"zc", best_t.zc}, {"nt", best_t.nt},
+                  {"pf", best_t.pf}, {"wt", best_t.wt}};
     write_cache(cache_path, cache);
     return SW_OK;
 }
@@ -397,7 +406,7 @@ sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cach
     if (it != cache.end()) {
         auto &v = it->second;
         if (b->ndim == 2 || const_shape_ok(v["tx"], v["nw"])) {
-            b->tiling = Tiling{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"] ? v["pf"] : 1};
+            b->tiling = Tiling{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"] ? v["pf"] : 1, 0};
             b->bpc = v["bpc"];
             return SW_OK;
         }
@@ -437,7 +446,7 @@ sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cach
         for (int zc : zc_candidates(zmin, b->r))
             for (int nt : {0, 1})
                 for (int pf : {1, 2}) {
-                b->tiling = Tiling{sh.first, sh.second, zc, nt, pf};
+                b->tiling = Tiling{sh.first, sh.second, zc, nt, pf, 0};
                 b->bpc = 0;
                 float ms = 0.0f;
                 sw_status st = time_cfg(ms);

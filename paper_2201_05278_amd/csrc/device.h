@@ -58,6 +58,7 @@ struct Tiling {
     int zc;                 // z-chunk length
     int nt;                 // 1: non-temporal loads/stores for the streamed arrays
     int pf;                 // planes of loads kept in flight ahead of the update (1 or 2)
+    int wt;                 // 1: wave tiles (each wave owns tx / nw rows, no block barrier)
 };
 
 hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);

@@ -5,28 +5,28 @@ namespace sw {
 
 hipError_t launch_const_r1(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r1(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r1(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r1(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r2(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r2(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r2(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r2(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r3(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r3(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r3(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r3(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r4(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r4(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r4(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r4(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r5(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r5(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r5(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r5(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r6(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r6(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r6(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r6(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r7(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r7(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r7(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r7(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r8(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r8(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r8(int, int, StencilParams &, hipStream_t);
+hipError_t launch_vd_r8(int, int, const Tiling &, StencilParams &, hipStream_t);
 
 hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {
@@ -61,16 +61,15 @@ hipError_t launch_const_batch(int r, int ndim, const Tiling &t, const StencilPar
 
 hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    (void)t;
     switch (r) {
-    case 1: return launch_vd_r1(scheme, ndim, P, s);
-    case 2: return launch_vd_r2(scheme, ndim, P, s);
-    case 3: return launch_vd_r3(scheme, ndim, P, s);
-    case 4: return launch_vd_r4(scheme, ndim, P, s);
-    case 5: return launch_vd_r5(scheme, ndim, P, s);
-    case 6: return launch_vd_r6(scheme, ndim, P, s);
-    case 7: return launch_vd_r7(scheme, ndim, P, s);
-    case 8: return launch_vd_r8(scheme, ndim, P, s);
+    case 1: return launch_vd_r1(scheme, ndim, t, P, s);
+    case 2: return launch_vd_r2(scheme, ndim, t, P, s);
+    case 3: return launch_vd_r3(scheme, ndim, t, P, s);
+    case 4: return launch_vd_r4(scheme, ndim, t, P, s);
+    case 5: return launch_vd_r5(scheme, ndim, t, P, s);
+    case 6: return launch_vd_r6(scheme, ndim, t, P, s);
+    case 7: return launch_vd_r7(scheme, ndim, t, P, s);
+    case 8: return launch_vd_r8(scheme, ndim, t, P, s);
     default: return hipErrorInvalidValue;
     }
 }

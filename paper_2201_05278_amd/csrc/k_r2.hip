@@ -15,9 +15,9 @@ hipError_t launch_batch_r2(int ndim, const Tiling &t, const StencilParams *shots
     return launch_batch_radius<2>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
 }
 
-hipError_t launch_vd_r2(int scheme, int ndim, StencilParams &P, hipStream_t s)
+hipError_t launch_vd_r2(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    return launch_vd_radius<2>(scheme, ndim, P, s);
+    return launch_vd_radius<2>(scheme, ndim, t, P, s);
 }
 
 }  // namespace sw

@@ -15,9 +15,9 @@ hipError_t launch_batch_r5(int ndim, const Tiling &t, const StencilParams *shots
     return launch_batch_radius<5>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
 }
 
-hipError_t launch_vd_r5(int scheme, int ndim, StencilParams &P, hipStream_t s)
+hipError_t launch_vd_r5(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    return launch_vd_radius<5>(scheme, ndim, P, s);
+    return launch_vd_radius<5>(scheme, ndim, t, P, s);
 }
 
 }  // namespace sw

@@ -26,6 +26,8 @@ T *at(void *ws, size_t off)
 Geom make_geom(const sw_plan *p);
 PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap::Pts &o, void *ws);
 bool const_shape_ok(int tx, int nw);
+bool vd_shape_ok(int tx, int nw);
+bool wave_shape_ok(int tx, int nw);
 int default_zc(const sw_plan *p, int tx, int64_t want);
 Tiling choose_tiling(const sw_plan *p);
 void fill_params(const sw_plan *p, void *ws, StencilParams &P);

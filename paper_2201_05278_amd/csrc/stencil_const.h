@@ -228,6 +228,191 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     }
 }
 
+// Wave tiles: every wavefront owns RW consecutive x rows of 64 columns and
+// marches along z on its own.  The x neighbours inside the wave's rows are the
+// centres of its own register queues; the R rows above and below come from
+// halo loads of the current plane; the y neighbours go through a row buffer in
+// LDS private to the wave.  No block-wide barrier is needed (a block is NWB
+// independent waves, RW * NWB rows).
+template <int R, int NDIM, int RW, int NWB, int MODE, int NT>
+__device__ __forceinline__ void const_wave_tile(const StencilParams &P, int bid)
+{
+    constexpr int HX = (NDIM == 3) ? R : 0;
+    constexpr int LY = 64 + 2 * R;
+    constexpr int YH = (RW * 2 * R + 63) / 64;      // y-halo items per lane
+    __shared__ float lds[NWB][RW][LY];
+
+    const Geom &g = P.g;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ty = bid % P.nty;
+    const int rest = bid / P.nty;
+    const int tx = rest % P.ntx;
+    const int zc = rest / P.ntx;
+    const int y0 = ty * 64;
+    const int y = y0 + lane;
+    const int xw = tx * (RW * NWB) + wave * RW;     // first row of this wave
+    const int zb = zc * P.zc;
+    const int ze = min(zb + P.zc, g.Z);
+    const int64_t sz = int64_t(g.px) * g.py;
+    const bool yin = y < g.Y;
+    const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
+    auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
+    const float *cur0 = P.cur + g.base;
+    float *nxt0 = P.nxt + g.base;
+    const float *k0 = P.K + g.base;
+    float(*T)[LY] = lds[wave];
+
+    unsigned ro[RW];
+    bool rin[RW];
+    int ex2[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int x = xw + i;
+        rin[i] = yin && x < g.X;
+        ro[i] = rin[i] ? off(x, y) : 0u;
+        const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
+        ex2[i] = ex * ex + ey * ey;
+    }
+    // halo rows xw-R .. xw-1 (lo) and xw+RW .. xw+RW+R-1 (hi)
+    unsigned hlo[HX > 0 ? HX : 1], hhi[HX > 0 ? HX : 1];
+    bool ilo[HX > 0 ? HX : 1], ihi[HX > 0 ? HX : 1];
+#pragma unroll
+    for (int j = 0; j < HX; ++j) {
+        const int xl = xw - R + j, xh = xw + RW + j;
+        ilo[j] = yin && xl >= 0 && xl < g.X;
+        ihi[j] = yin && xh < g.X;
+        hlo[j] = ilo[j] ? off(xl, y) : 0u;
+        hhi[j] = ihi[j] ? off(xh, y) : 0u;
+    }
+    // y-halo items: RW rows x 2R columns spread over the lanes
+    unsigned hyo[YH];
+    bool hyin[YH], hyok[YH];
+    int hyrow[YH], hycol[YH];
+#pragma unroll
+    for (int s = 0; s < YH; ++s) {
+        const int e = lane + 64 * s;
+        hyok[s] = e < RW * 2 * R;
+        const int row = e / (2 * R), c = e % (2 * R);
+        const int yy = (c < R) ? y0 - R + c : y0 + 64 + c - R;
+        const int x = xw + row;
+        hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
+        hyrow[s] = hyok[s] ? row : 0;
+        hycol[s] = (c < R) ? c : 64 + c;
+        hyo[s] = hyin[s] ? off(x, yy) : 0u;
+    }
+
+    float q[RW][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+        const int z = zb - R + k;
+        const bool zin = z >= 0 && z < g.Z;
+        const float *pl = cur0 + int64_t(z) * sz;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) q[i][k] = (rin[i] && zin) ? pl[ro[i]] : 0.0f;
+    }
+
+    struct Slot {
+        float f[RW], p[RW], k[RW], a[RW], b[RW], d[RW], g[RW];
+        float lo[HX > 0 ? HX : 1], hi[HX > 0 ? HX : 1], hy[YH];
+    };
+    auto load = [&](int z, Slot &S) {
+        const int zf = z + R;
+        const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
+        const float *pc = cur0 + int64_t(z) * sz;
+        const float *pf = cur0 + int64_t(zf) * sz;
+        const float *pn = nxt0 + int64_t(z) * sz;
+        const float *pk = k0 + int64_t(z) * sz;
+        const bool fin = zf < g.Z;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            S.f[i] = (rin[i] && fin) ? pf[ro[i]] : 0.0f;
+            S.p[i] = rin[i] ? ld_stream<NT>(pn + ro[i]) : 0.0f;
+            S.k[i] = rin[i] ? ld_stream<NT>(pk + ro[i]) : 0.0f;
+            const int d2 = ez * ez + ex2[i];
+            S.a[i] = 1.0f;
+            S.b[i] = 1.0f;
+            if (rin[i] && d2 > 0) {
+                const float2 ab = P.damp[d2];
+                S.a[i] = ab.x;
+                S.b[i] = ab.y;
+            }
+            if constexpr (MODE == MODE_IMAGE) {
+                const int64_t o = int64_t(z) * sz + g.base + ro[i];
+                S.d[i] = rin[i] ? ld_stream<NT>(P.store + o) : 0.0f;
+                S.g[i] = rin[i] ? ld_stream<NT>(P.grad + o) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < HX; ++j) {
+            S.lo[j] = ilo[j] ? pc[hlo[j]] : 0.0f;
+            S.hi[j] = ihi[j] ? pc[hhi[j]] : 0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < YH; ++s) S.hy[s] = hyin[s] ? pc[hyo[s]] : 0.0f;
+    };
+
+    Slot S;
+    load(zb, S);
+    for (int z = zb; z < ze; ++z) {
+        const Slot W = S;
+        if (z + 1 < ze) load(z + 1, S);
+#pragma unroll
+        for (int i = 0; i < RW; ++i) q[i][2 * R] = W.f[i];
+        // y neighbours through the wave's own LDS rows (DS operations of one
+        // wave complete in order; the fence keeps the compiler from moving
+        // this plane's reads across the writes)
+#pragma unroll
+        for (int i = 0; i < RW; ++i) T[i][R + lane] = q[i][R];
+#pragma unroll
+        for (int s = 0; s < YH; ++s)
+            if (hyok[s]) T[hyrow[s]][hycol[s]] = W.hy[s];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        float *pn = nxt0 + int64_t(z) * sz;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const float c = q[i][R];
+            float lap = P.c0 * c;
+#pragma unroll
+            for (int j = 1; j <= R; ++j) lap = fmaf(P.cz[j], q[i][R + j] + q[i][R - j], lap);
+            if constexpr (NDIM == 3) {
+#pragma unroll
+                for (int j = 1; j <= R; ++j) {
+                    const float up = (i + j < RW) ? q[(i + j) % RW][R] : W.hi[(i + j - RW) % (HX > 0 ? HX : 1)];
+                    const float dn = (i - j >= 0) ? q[(i - j + RW) % RW][R] : W.lo[(R + i - j) % (HX > 0 ? HX : 1)];
+                    lap = fmaf(P.cx[j], up + dn, lap);
+                }
+            }
+#pragma unroll
+            for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[i][R + lane + j] + T[i][R + lane - j], lap);
+            const float out = W.a[i] * fmaf(W.k[i], lap, 2.0f * c) - W.b[i] * W.p[i];
+            if (rin[i]) {
+                st_stream<NT>(out, pn + ro[i]);
+                const int64_t o = int64_t(z) * sz + g.base + ro[i];
+                if constexpr (MODE == MODE_STORE) st_stream<NT>(W.k[i] * lap, P.store + o);
+                if constexpr (MODE == MODE_IMAGE)
+                    st_stream<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), P.grad + o);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) q[i][k] = q[i][k + 1];
+    }
+}
+
+template <int R, int NDIM, int RW, int NWB, int MODE, int NT>
+__global__ void __launch_bounds__(64 * NWB) k_const_wave(StencilParams P)
+{
+    const_wave_tile<R, NDIM, RW, NWB, MODE, NT>(P, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
 __global__ void __launch_bounds__(64 * NW) k_const(StencilParams P)
 {
@@ -278,10 +463,32 @@ hipError_t launch_const_shape(int mode, StencilParams &P, hipStream_t s)
     return hipGetLastError();
 }
 
+// Wave-tile shapes (rows per wave, waves per block).
+#define SW_WAVE_SHAPES(X) X(4, 4) X(8, 4) X(4, 1) X(8, 1) X(8, 2)
+
+template <int R, int NDIM, int RW, int NWB, int NT>
+hipError_t launch_wave_shape(int mode, StencilParams &P, hipStream_t s)
+{
+    const dim3 grid(P.ntx * P.nty * P.nzc), block(64 * NWB);
+    switch (mode) {
+    case MODE_FWD: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_FWD, NT>), grid, block, 0, s, P); break;
+    case MODE_STORE: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_STORE, NT>), grid, block, 0, s, P); break;
+    default: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_IMAGE, NT>), grid, block, 0, s, P); break;
+    }
+    return hipGetLastError();
+}
+
 template <int R, int NT, int PF>
 hipError_t launch_const_v(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {
     if (ndim == 2) return launch_const_shape<R, 2, 1, 1, NT, PF>(mode, P, s);
+    if (t.wt) {
+#define SW_X(RWV, NWV) \
+        if (t.tx == RWV * NWV && t.nw == NWV) return launch_wave_shape<R, 3, RWV, NWV, NT>(mode, P, s);
+        SW_WAVE_SHAPES(SW_X)
+#undef SW_X
+        return hipErrorInvalidValue;
+    }
 #define SW_X(TXV, NWV) \
     if (t.tx == TXV && t.nw == NWV) return launch_const_shape<R, 3, TXV, NWV, NT, PF>(mode, P, s);
     SW_CONST_SHAPES(SW_X)

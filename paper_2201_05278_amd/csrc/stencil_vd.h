@@ -23,12 +23,13 @@
 #pragma once
 
 #include "device.h"
+#include "stencil_const.h"
 
 namespace sw {
 
 __device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-template <int R, int NDIM, int TX, int NW>
+template <int R, int NDIM, int TX, int NW, int NT>
 __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
 {
     static_assert(TX % NW == 0, "rows must split evenly over waves");
@@ -38,11 +39,11 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     constexpr int LY = 64 + 2 * H2;
     constexpr int LX = TX + 2 * HX;
     constexpr int FY = 64 + 2 * R;
-    constexpr int NT = 64 * NW;
+    constexpr int NTH = 64 * NW;
     constexpr int NCOL = RPT + 4 * R - 2;
     constexpr int NFX = RPT + 2 * R - 1;
     constexpr int HXN = (NDIM == 3) ? (2 * HX + NW - 1) / NW : 0;
-    constexpr int YHN = (TX * 2 * H2 + NT - 1) / NT;
+    constexpr int YHN = (TX * 2 * H2 + NTH - 1) / NTH;
     __shared__ float sp[LX][LY];
     __shared__ float sb[LX][LY];
     __shared__ float sfy[TX][FY];
@@ -64,24 +65,27 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const bool yin = y < g.Y;
     const int yc = clampi(y, 0, g.Y - 1);
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
-    const float *__restrict__ cur = P.cur;
-    const float *__restrict__ bm = P.aux;
-    float *__restrict__ nxt = P.nxt;
+    // plane base pointers + unsigned 32-bit lane offsets off(x, y) = xy0 + x py + y
+    auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
+    const float *cur = P.cur + g.base;
+    const float *bm = P.aux + g.base;
+    float *nxt = P.nxt + g.base;
+    const float *km = P.K + g.base;
 
-    int64_t roff[RPT], rboff[RPT];
+    unsigned roff[RPT], rboff[RPT];
     bool rin[RPT];
     int ex2[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         rin[i] = yin && x < g.X;
-        roff[i] = g.origin + int64_t(x) * g.py + y;
-        rboff[i] = g.origin + int64_t(clampi(x, 0, g.X - 1)) * g.py + yc;
+        roff[i] = rin[i] ? off(x, y) : 0u;
+        rboff[i] = off(clampi(x, 0, g.X - 1), yc);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = ex * ex + ey * ey;
     }
     // x-halo rows (3D): 2R rows on each side, one lane per column
-    int64_t hxo[HXN > 0 ? HXN : 1], hxbo[HXN > 0 ? HXN : 1];
+    unsigned hxo[HXN > 0 ? HXN : 1], hxbo[HXN > 0 ? HXN : 1];
     bool hxin[HXN > 0 ? HXN : 1], hxok[HXN > 0 ? HXN : 1];
     int hxrow[HXN > 0 ? HXN : 1];
 #pragma unroll
@@ -91,16 +95,16 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const int x = (hr < HX) ? x0 - HX + hr : x0 + TX + hr - HX;
         hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
         hxrow[s] = (hr < HX) ? hr : TX + hr;
-        hxo[s] = g.origin + int64_t(x) * g.py + y;
-        hxbo[s] = g.origin + int64_t(clampi(x, 0, g.X - 1)) * g.py + yc;
+        hxo[s] = hxin[s] ? off(x, y) : 0u;
+        hxbo[s] = off(clampi(x, 0, g.X - 1), yc);
     }
     // y-halo columns: 2R on each side of every tile row
-    int64_t hyo[YHN], hybo[YHN];
+    unsigned hyo[YHN], hybo[YHN];
     bool hyin[YHN], hyok[YHN];
     int hyrow[YHN], hycol[YHN];
 #pragma unroll
     for (int s = 0; s < YHN; ++s) {
-        const int e = threadIdx.x + s * NT;
+        const int e = threadIdx.x + s * NTH;
         hyok[s] = e < TX * 2 * H2;
         const int row = e / (2 * H2), c = e % (2 * H2);
         const int yy = (c < H2) ? y0 - H2 + c : y0 + 64 + c - H2;
@@ -108,15 +112,15 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
         hyrow[s] = HX + row;
         hycol[s] = (c < H2) ? c : 64 + c;
-        hyo[s] = g.origin + int64_t(x) * g.py + yy;
-        hybo[s] = g.origin + int64_t(clampi(x, 0, g.X - 1)) * g.py + clampi(yy, 0, g.Y - 1);
+        hyo[s] = hyin[s] ? off(x, yy) : 0u;
+        hybo[s] = off(clampi(x, 0, g.X - 1), clampi(yy, 0, g.Y - 1));
     }
 
     auto pz_ = [&](int i, int z) -> float {
-        return (rin[i] && z >= 0 && z < g.Z) ? cur[roff[i] + int64_t(z) * sz] : 0.0f;
+        return (rin[i] && z >= 0 && z < g.Z) ? (cur + int64_t(z) * sz)[roff[i]] : 0.0f;
     };
     auto bz_ = [&](int i, int z) -> float {
-        return bm[rboff[i] + int64_t(clampi(z, 0, g.Z - 1)) * sz];
+        return (bm + int64_t(clampi(z, 0, g.Z - 1)) * sz)[rboff[i]];
     };
 
     // queues: pq[k] = p(z + k), bq[k] = b(z + k), fq[k] = z-flux at face (z - R + k) + 1/2
@@ -147,8 +151,8 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const int64_t zo = int64_t(z) * sz;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            np_[i] = rin[i] ? nxt[roff[i] + zo] : 0.0f;
-            nk[i] = rin[i] ? P.K[roff[i] + zo] : 0.0f;
+            np_[i] = rin[i] ? ld_stream<NT>(nxt + zo + roff[i]) : 0.0f;
+            nk[i] = rin[i] ? ld_stream<NT>(km + zo + roff[i]) : 0.0f;
             const int d2 = ez * ez + ex2[i];
             na[i] = 1.0f;
             nb[i] = 1.0f;
@@ -160,13 +164,13 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         }
 #pragma unroll
         for (int s = 0; s < HXN; ++s) {
-            nhxp[s] = hxin[s] ? cur[hxo[s] + zo] : 0.0f;
-            nhxb[s] = hxok[s] ? bm[hxbo[s] + zo] : 0.0f;
+            nhxp[s] = hxin[s] ? (cur + zo)[hxo[s]] : 0.0f;
+            nhxb[s] = hxok[s] ? (bm + zo)[hxbo[s]] : 0.0f;
         }
 #pragma unroll
         for (int s = 0; s < YHN; ++s) {
-            nhyp[s] = hyin[s] ? cur[hyo[s] + zo] : 0.0f;
-            nhyb[s] = hyok[s] ? bm[hybo[s] + zo] : 0.0f;
+            nhyp[s] = hyin[s] ? (cur + zo)[hyo[s]] : 0.0f;
+            nhyb[s] = hyok[s] ? (bm + zo)[hybo[s]] : 0.0f;
         }
     };
 
@@ -288,7 +292,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
                 const float lap = dzs + dx[i] + dys;
                 const float c = pq[i][0];
                 const float out = pa[i] * fmaf(pk[i], lap, 2.0f * c) - pb[i] * pp[i];
-                if (rin[i]) nxt[roff[i] + int64_t(z) * sz] = out;
+                if (rin[i]) st_stream<NT>(out, nxt + int64_t(z) * sz + roff[i]);
             }
         }
 #pragma unroll
@@ -302,7 +306,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     }
 }
 
-template <int R, int NDIM, int TX, int NW>
+template <int R, int NDIM, int TX, int NW, int NT>
 __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 {
     static_assert(TX % NW == 0, "rows must split evenly over waves");
@@ -310,9 +314,9 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
     constexpr int HXR = (NDIM == 3) ? R : 0;
     constexpr int LY = 64 + 2 * R;
     constexpr int LX = TX + 2 * HXR;
-    constexpr int NT = 64 * NW;
+    constexpr int NTH = 64 * NW;
     constexpr int HXN = (NDIM == 3) ? (2 * R + NW - 1) / NW : 0;
-    constexpr int YHN = (TX * 2 * R + NT - 1) / NT;
+    constexpr int YHN = (TX * 2 * R + NTH - 1) / NTH;
     __shared__ float sp[2][LX][LY];
     __shared__ float sr[2][LX][LY];
 
@@ -333,23 +337,26 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
     const bool yin = y < g.Y;
     const int yc = clampi(y, 0, g.Y - 1);
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
-    const float *__restrict__ cur = P.cur;
-    const float *__restrict__ rm = P.aux;
-    float *__restrict__ nxt = P.nxt;
+    // plane base pointers + unsigned 32-bit lane offsets off(x, y) = xy0 + x py + y
+    auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
+    const float *cur = P.cur + g.base;
+    const float *rm = P.aux + g.base;
+    float *nxt = P.nxt + g.base;
+    const float *km = P.K + g.base;
 
-    int64_t roff[RPT], rroff[RPT];
+    unsigned roff[RPT], rroff[RPT];
     bool rin[RPT];
     int ex2[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         rin[i] = yin && x < g.X;
-        roff[i] = g.origin + int64_t(x) * g.py + y;
-        rroff[i] = g.origin + int64_t(clampi(x, 0, g.X - 1)) * g.py + yc;
+        roff[i] = rin[i] ? off(x, y) : 0u;
+        rroff[i] = off(clampi(x, 0, g.X - 1), yc);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = ex * ex + ey * ey;
     }
-    int64_t hxo[HXN > 0 ? HXN : 1], hxro[HXN > 0 ? HXN : 1];
+    unsigned hxo[HXN > 0 ? HXN : 1], hxro[HXN > 0 ? HXN : 1];
     bool hxin[HXN > 0 ? HXN : 1], hxok[HXN > 0 ? HXN : 1];
     int hxrow[HXN > 0 ? HXN : 1];
 #pragma unroll
@@ -359,15 +366,15 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         const int x = (hr < R) ? x0 - R + hr : x0 + TX + hr - R;
         hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
         hxrow[s] = (hr < R) ? hr : TX + hr;
-        hxo[s] = g.origin + int64_t(x) * g.py + y;
-        hxro[s] = g.origin + int64_t(clampi(x, 0, g.X - 1)) * g.py + yc;
+        hxo[s] = hxin[s] ? off(x, y) : 0u;
+        hxro[s] = off(clampi(x, 0, g.X - 1), yc);
     }
-    int64_t hyo[YHN], hyro[YHN];
+    unsigned hyo[YHN], hyro[YHN];
     bool hyin[YHN], hyok[YHN];
     int hyrow[YHN], hycol[YHN];
 #pragma unroll
     for (int s = 0; s < YHN; ++s) {
-        const int e = threadIdx.x + s * NT;
+        const int e = threadIdx.x + s * NTH;
         hyok[s] = e < TX * 2 * R;
         const int row = e / (2 * R), c = e % (2 * R);
         const int yy = (c < R) ? y0 - R + c : y0 + 64 + c - R;
@@ -375,8 +382,8 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
         hyrow[s] = HXR + row;
         hycol[s] = (c < R) ? c : 64 + c;
-        hyo[s] = g.origin + int64_t(x) * g.py + yy;
-        hyro[s] = g.origin + int64_t(clampi(x, 0, g.X - 1)) * g.py + clampi(yy, 0, g.Y - 1);
+        hyo[s] = hyin[s] ? off(x, yy) : 0u;
+        hyro[s] = off(clampi(x, 0, g.X - 1), clampi(yy, 0, g.Y - 1));
     }
 
     float q[RPT][2 * R + 1], qr[RPT][2 * R + 1];
@@ -385,8 +392,8 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 #pragma unroll
         for (int k = 0; k < 2 * R; ++k) {
             const int z = zb - R + k;
-            q[i][k] = (rin[i] && z >= 0 && z < g.Z) ? cur[roff[i] + int64_t(z) * sz] : 0.0f;
-            qr[i][k] = rm[rroff[i] + int64_t(clampi(z, 0, g.Z - 1)) * sz];
+            q[i][k] = (rin[i] && z >= 0 && z < g.Z) ? (cur + int64_t(z) * sz)[roff[i]] : 0.0f;
+            qr[i][k] = (rm + int64_t(clampi(z, 0, g.Z - 1)) * sz)[rroff[i]];
         }
 
     float nf[RPT], nfr[RPT], np_[RPT], nk[RPT], na[RPT], nb[RPT];
@@ -399,8 +406,8 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         for (int i = 0; i < RPT; ++i) {
             nf[i] = (rin[i] && zf < g.Z) ? cur[roff[i] + int64_t(zf) * sz] : 0.0f;
             nfr[i] = rm[rroff[i] + int64_t(min(zf, g.Z - 1)) * sz];
-            np_[i] = rin[i] ? nxt[roff[i] + zo] : 0.0f;
-            nk[i] = rin[i] ? P.K[roff[i] + zo] : 0.0f;
+            np_[i] = rin[i] ? ld_stream<NT>(nxt + zo + roff[i]) : 0.0f;
+            nk[i] = rin[i] ? ld_stream<NT>(km + zo + roff[i]) : 0.0f;
             const int d2 = ez * ez + ex2[i];
             na[i] = 1.0f;
             nb[i] = 1.0f;
@@ -412,13 +419,13 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         }
 #pragma unroll
         for (int s = 0; s < HXN; ++s) {
-            nhx[s] = hxin[s] ? cur[hxo[s] + zo] : 0.0f;
-            nhxr[s] = hxok[s] ? rm[hxro[s] + zo] : 0.0f;
+            nhx[s] = hxin[s] ? (cur + zo)[hxo[s]] : 0.0f;
+            nhxr[s] = hxok[s] ? (rm + zo)[hxro[s]] : 0.0f;
         }
 #pragma unroll
         for (int s = 0; s < YHN; ++s) {
-            nhy[s] = hyin[s] ? cur[hyo[s] + zo] : 0.0f;
-            nhyr[s] = hyok[s] ? rm[hyro[s] + zo] : 0.0f;
+            nhy[s] = hyin[s] ? (cur + zo)[hyo[s]] : 0.0f;
+            nhyr[s] = hyok[s] ? (rm + zo)[hyro[s]] : 0.0f;
         }
     };
 
@@ -498,7 +505,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
             const float grad = fmaf(drz, dpz, fmaf(drx, dpx, dry * dpy));
             const float Lp = lap - grad / qr[i][R];
             const float out = pa[i] * fmaf(pk[i], Lp, 2.0f * c) - pb[i] * pp[i];
-            if (rin[i]) nxt[roff[i] + int64_t(z) * sz] = out;
+            if (rin[i]) st_stream<NT>(out, nxt + int64_t(z) * sz + roff[i]);
         }
         buf ^= 1;
 #pragma unroll
@@ -511,18 +518,33 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
     }
 }
 
-template <int R>
-hipError_t launch_vd_radius(int scheme, int ndim, StencilParams &P, hipStream_t s)
+// Tile shapes (rows, waves) of the variable-density kernels in 3D; 2D uses (1, 1).
+#define SW_VD_SHAPES(X) X(16, 8) X(8, 8) X(8, 4) X(16, 4)
+
+template <int R, int NT>
+hipError_t launch_vd_nt(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
     const dim3 grid(P.ntx * P.nty * P.nzc);
-    if (scheme == 1) {
-        if (ndim == 2) hipLaunchKernelGGL((k_stag<R, 2, 1, 1>), grid, dim3(64), 0, s, P);
-        else hipLaunchKernelGGL((k_stag<R, 3, 16, 8>), grid, dim3(512), 0, s, P);
-    } else {
-        if (ndim == 2) hipLaunchKernelGGL((k_cent<R, 2, 1, 1>), grid, dim3(64), 0, s, P);
-        else hipLaunchKernelGGL((k_cent<R, 3, 16, 8>), grid, dim3(512), 0, s, P);
+    if (ndim == 2) {
+        if (scheme == 1) hipLaunchKernelGGL((k_stag<R, 2, 1, 1, NT>), grid, dim3(64), 0, s, P);
+        else hipLaunchKernelGGL((k_cent<R, 2, 1, 1, NT>), grid, dim3(64), 0, s, P);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+#define SW_X(TXV, NWV)                                                                             \
+    if (t.tx == TXV && t.nw == NWV) {                                                              \
+        if (scheme == 1) hipLaunchKernelGGL((k_stag<R, 3, TXV, NWV, NT>), grid, dim3(64 * NWV), 0, s, P); \
+        else hipLaunchKernelGGL((k_cent<R, 3, TXV, NWV, NT>), grid, dim3(64 * NWV), 0, s, P);    \
+        return hipGetLastError();                                                                  \
+    }
+    SW_VD_SHAPES(SW_X)
+#undef SW_X
+    return hipErrorInvalidValue;
+}
+
+template <int R>
+hipError_t launch_vd_radius(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
+{
+    return t.nt ? launch_vd_nt<R, 1>(scheme, ndim, t, P, s) : launch_vd_nt<R, 0>(scheme, ndim, t, P, s);
 }
 
 }  // namespace sw

@@ -184,10 +184,17 @@ class Propagator:
         return self
 
     # ---- tiling -------------------------------------------------------------
-    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0):
-        """Stencil tile shape, z-chunk length, cache policy and prefetch
-        distance (0 / -1: default)."""
-        L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, tx, nw, zc, nt, pf))
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0):
+        """Stencil tile shape, z-chunk length, cache policy, prefetch distance
+        and wave-tile mode (0 / -1: default)."""
+        t = L.Tiling(tx, nw, zc, nt, pf, wt)
+        L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, ctypes.byref(t)))
+
+    @property
+    def tiling(self):
+        t = L.Tiling()
+        L.check("sw_plan_get_tiling", L.lib().sw_plan_get_tiling(self._plan, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in L.Tiling._fields_}
 
     def autotune(self, cache_path=None):
         """Time candidate tilings on scratch buffers and keep the fastest (or

@@ -31,9 +31,11 @@ def test_tilings_are_bitwise_identical():
     torch.cuda.synchronize()
     u_ref = prop.grid_view(ref.fields[ref.current]).clone()
     tr_ref = ref.traces.clone()
-    for tx, nw, zc, nt in [(8, 4, 0, 0), (32, 8, 13, 1), (16, 8, 100, 1), (16, 4, 9, 0)]:
-        print(f"case: tiling {tx}x{nw} zc={zc} nt={nt}", flush=True)
-        prop.set_tiling(tx, nw, zc, nt)
+    for tx, nw, zc, nt, pf, wt in [(8, 4, 0, 0, 1, 0), (32, 8, 13, 1, 2, 0), (16, 8, 100, 1, 1, 0),
+                                   (16, 4, 9, 0, 2, 0), (8, 8, 20, 1, 2, 0), (16, 4, 17, 1, 0, 1),
+                                   (4, 1, 0, 0, 0, 1), (8, 1, 31, 1, 0, 1)]:
+        print(f"case: tiling {tx}x{nw} zc={zc} nt={nt} pf={pf} wave={wt}", flush=True)
+        prop.set_tiling(tx, nw, zc, nt, pf, wt)
         r = prop.forward(wav)
         torch.cuda.synchronize()
         assert torch.equal(r.traces, tr_ref)
@@ -72,6 +74,7 @@ def test_autotune_keeps_results_and_uses_cache(tmp_path):
     text = open(cache).read()
     assert "plan_s0_r2_d3" in text
     prop.set_tiling()            # back to defaults, then read the choice from the cache
+    assert prop.tiling["tx"] > 0
     prop.autotune(cache)
     again = prop.forward(wav)
     torch.cuda.synchronize()
