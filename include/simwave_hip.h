@@ -204,8 +204,16 @@ typedef struct sw_fwd_io {
     int32_t use_graph;        /* 1: capture the step loop in a HIP graph and launch it */
     float *stencil_ms;        /* host [nsteps_run] or NULL: if given, HIP events are recorded
                                  on `stream` around each stencil launch, the call waits for
-                                 them and writes each launch's duration in milliseconds
+                                 them and writes, for every step, the duration in
+                                 milliseconds of the launch that advanced it divided by
+                                 the number of steps that launch advanced (1 or 2)
                                  (not combinable with use_graph) */
+    float *field2[2];         /* device, field_elems floats each, or NULL: two more
+                                 wavefield buffers.  With both given and a tiling of
+                                 ts = 2, steps run in two-step sweeps (four steps at a
+                                 time: field -> field2 -> field); remaining steps and
+                                 all other cases run singly.  Contents on return are
+                                 unspecified; the result is in field[] as above. */
 } sw_fwd_io;
 
 sw_status sw_forward(sw_plan *plan, const sw_fwd_io *io, void *stream);
@@ -250,9 +258,16 @@ sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
  *           -1: default
  *   pf      planes of loads in flight ahead of the update (1 or 2; 0: default;
  *           block tiles only)
- *   wt      1: wave tiles (see tx, nw) */
+ *   wt      1: wave tiles (see tx, nw)
+ *   ts      time steps per sweep: 0 default, 1, or 2 (constant density, 3D,
+ *           forward only: one launch reads p^n, p^{n-1}, K and writes
+ *           p^{n+1}, p^{n+2}, evaluating the first step also on R ghost rows
+ *           and columns around the tile; the tile is tx rows x (64 - 2R)
+ *           columns; shapes (8,4), (16,8), (8,8), (16,4) where the register
+ *           queues fit: (tx/nw)(5R+5) + ceil(2R/nw)(3R+3) <= 95, so up to R = 7).  Takes
+ *           effect when sw_fwd_io.field2 is given. */
 typedef struct sw_tiling {
-    int32_t tx, nw, zc, nt, pf, wt;
+    int32_t tx, nw, zc, nt, pf, wt, ts;
 } sw_tiling;
 
 /* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan. */

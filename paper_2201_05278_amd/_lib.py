@@ -53,7 +53,8 @@ class FwdIO(ctypes.Structure):
     _fields_ = [("workspace", c_void_p), ("wavelet", c_void_p), ("field", c_void_p * 2),
                 ("traces", c_void_p), ("snaps", c_void_p), ("saving_stride", c_int32),
                 ("ckpt", c_void_p), ("ckpt_every", c_int32), ("step0", c_int32),
-                ("nsteps_run", c_int32), ("use_graph", c_int32), ("stencil_ms", c_float_p)]
+                ("nsteps_run", c_int32), ("use_graph", c_int32), ("stencil_ms", c_float_p),
+                ("field2", c_void_p * 2)]
 
 
 class AdjIO(ctypes.Structure):
@@ -65,7 +66,7 @@ class AdjIO(ctypes.Structure):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("tx", c_int32), ("nw", c_int32), ("zc", c_int32), ("nt", c_int32), ("pf", c_int32),
-                ("wt", c_int32)]
+                ("wt", c_int32), ("ts", c_int32)]
 
 
 class BatchIO(ctypes.Structure):

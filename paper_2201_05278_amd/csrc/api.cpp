@@ -82,11 +82,25 @@ bool vd_shape_ok(int tx, int nw)
     return (tx == 16 && nw == 8) || (tx == 8 && nw == 8) || (tx == 8 && nw == 4) || (tx == 16 && nw == 4);
 }
 
+// Two-step sweep shapes whose register queues fit (same rule as the kernel).
+bool tb_shape_ok(int r, int tx, int nw)
+{
+    const bool listed = (tx == 8 && nw == 4) || (tx == 16 && nw == 8) || (tx == 8 && nw == 8) ||
+                        (tx == 16 && nw == 4);
+    return listed && (tx / nw) * (5 * r + 5) + ((2 * r + nw - 1) / nw) * (3 * r + 3) <= 95;
+}
+
+// Columns of a tile along y: 64, or 64 - 2R for the two-step sweep.
+static int tile_cols(const sw_plan *p, int ts)
+{
+    return ts == 2 ? 64 - 2 * p->r : 64;
+}
+
 // z-chunk length giving about `want` blocks in total (at least 4R planes).
-int default_zc(const sw_plan *p, int tx, int64_t want)
+int default_zc(const sw_plan *p, int tx, int64_t want, int ts)
 {
     const int ntx = (p->dims[1] + tx - 1) / tx;
-    const int nty = (p->dims[2] + 63) / 64;
+    const int nty = (p->dims[2] + tile_cols(p, ts) - 1) / tile_cols(p, ts);
     const int64_t tiles = int64_t(ntx) * nty;
     const int nzc = int(std::max<int64_t>(1, (want + tiles - 1) / tiles));
     const int zc = (p->dims[0] + nzc - 1) / nzc;
@@ -108,13 +122,20 @@ Tiling choose_tiling(const sw_plan *p)
         t.tx = p->tile_tx;
         t.nw = p->tile_nw;
         t.wt = p->tile_wt;
+        t.ts = p->tile_ts == 2 ? 2 : 1;
+    } else if (p->tile_ts == 2) {
+        t.tx = 8;
+        t.nw = tb_shape_ok(p->r, 8, 4) ? 4 : 8;
+        t.ts = 2;
     } else {
         t.tx = 8;
         t.nw = 4;
     }
+    if (t.ts == 0) t.ts = 1;
     // z chunks of about 74 planes (fewer if the grid has few tiles per plane)
     t.zc = p->tile_zc ? std::min(p->tile_zc, p->dims[0])
-                      : std::min(std::min(74, p->dims[0]), default_zc(p, t.tx, p->ndim == 2 ? 1024 : 4096));
+                      : std::min(std::min(74, p->dims[0]),
+                                 default_zc(p, t.tx, p->ndim == 2 ? 1024 : 4096, t.ts));
     t.nt = p->tile_nt < 0 ? kDefaultNT : p->tile_nt;
     t.pf = p->tile_pf ? p->tile_pf : kDefaultPF;
     return t;
@@ -127,6 +148,7 @@ void fill_params(const sw_plan *p, void *ws, StencilParams &P)
     P.K = at<float>(ws, p->ws.model_k);
     P.aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
     P.damp = at<float2>(ws, p->ws.damp);
+    P.ndamp = p->damp_n;
     double c0 = 0.0;
     const double h2z = p->hh[0] * p->hh[0], h2x = p->hh[1] * p->hh[1], h2y = p->hh[2] * p->hh[2];
     c0 += p->v2[0] / h2z + p->v2[0] / h2y;
@@ -147,18 +169,68 @@ void fill_params(const sw_plan *p, void *ws, StencilParams &P)
 
 void set_tiles(const sw_plan *p, const Tiling &t, StencilParams &P)
 {
+    const int cols = tile_cols(p, t.ts);
+    // a z window (chunk plus 4R planes) stays below 2^31 bytes: 32-bit buffer offsets
+    const int64_t pbytes = int64_t(p->pad[1]) * p->pad[2] * 4;
+    const int zmax = int(std::max<int64_t>(1, (int64_t(1) << 31) / pbytes - 4 * p->r - 2));
     P.ntx = (p->dims[1] + t.tx - 1) / t.tx;
-    P.nty = (p->dims[2] + 63) / 64;
-    P.zc = t.zc;
-    P.nzc = (p->dims[0] + t.zc - 1) / t.zc;
+    P.nty = (p->dims[2] + cols - 1) / cols;
+    P.zc = std::min(t.zc, zmax);
+    P.nzc = (p->dims[0] + P.zc - 1) / P.zc;
 }
 
 hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s)
 {
-    const Tiling t = choose_tiling(p);
+    Tiling t = choose_tiling(p);
+    t.ts = 1;
     set_tiles(p, t, P);
     if (p->prob.scheme == SW_CONST) return launch_const(p->r, p->ndim, mode, t, P, s);
     return launch_vd(p->prob.scheme, p->r, p->ndim, t, P, s);
+}
+
+bool two_step_ready(const sw_plan *p, const sw_fwd_io *io)
+{
+    return p->ndim == 3 && p->prob.scheme == SW_CONST && io->field2[0] && io->field2[1] &&
+           choose_tiling(p).ts == 2;
+}
+
+hipError_t stencil_two(const sw_plan *p, const sw_fwd_io *io, int n, const float *cur, const float *prv,
+                       float *out1, float *out2, bool sources, hipStream_t s)
+{
+    void *ws = io->workspace;
+    StencilParams P;
+    fill_params(p, ws, P);
+    const Tiling t = choose_tiling(p);
+    set_tiles(p, t, P);
+    P.cur = cur;
+    P.nxt = const_cast<float *>(prv);
+    TwoStepParams T{};
+    T.out1 = out1;
+    T.out2 = out2;
+    const PointTableDev src = table_dev(p, p->src, p->ws.src, ws);
+    T.nuniq = sources ? src.nuniq : 0;
+    T.unode = src.unode;
+    float *inj = at<float>(ws, p->ws.src.inj);
+    T.inj = inj;
+    T.box[0] = T.box[2] = T.box[4] = 1;       // empty box
+    T.box[1] = T.box[3] = T.box[5] = 0;
+    if (T.nuniq > 0) {
+        const int64_t plane = int64_t(p->pad[1]) * p->pad[2];
+        T.box[0] = T.box[2] = T.box[4] = 1 << 30;
+        T.box[1] = T.box[3] = T.box[5] = -1;
+        for (const int64_t e : p->src.unode) {
+            const int64_t rel = e - p->origin;
+            const int c[3] = {int(rel / plane), int((rel / p->pad[2]) % p->pad[1]), int(rel % p->pad[2])};
+            for (int a = 0; a < 3; ++a) {
+                T.box[2 * a] = std::min(T.box[2 * a], c[a]);
+                T.box[2 * a + 1] = std::max(T.box[2 * a + 1], c[a]);
+            }
+        }
+        const hipError_t e = launch_inject_values(src, io->wavelet + size_t(n) * src.count,
+                                                  io->wavelet + size_t(n + 1) * src.count, inj, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_const_two(p->r, t, P, T, s);
 }
 
 sw_status check_problem(const sw_problem *q)
@@ -290,9 +362,19 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
 {
     set_error("");
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
-    sw_tiling d{0, 0, 0, -1, 0, 0};
+    sw_tiling d{0, 0, 0, -1, 0, 0, 0};
     if (t) d = *t;
     if (d.zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
+    if (d.ts < 0 || d.ts > 2) return fail(SW_ERR_ARG, "ts must be 0, 1 or 2");
+    if (d.ts == 2) {
+        if (p->ndim != 3 || p->prob.scheme != SW_CONST)
+            return fail(SW_ERR_UNSUPPORTED, "two-step sweeps cover 3D constant density");
+        if (d.wt) return fail(SW_ERR_ARG, "two-step sweeps use block tiles");
+        if ((d.tx || d.nw) && !tb_shape_ok(p->r, d.tx, d.nw))
+            return fail(SW_ERR_UNSUPPORTED, "tile shape not provided for two-step sweeps at this order");
+        if (!d.tx && !d.nw && !tb_shape_ok(p->r, 8, 4) && !tb_shape_ok(p->r, 8, 8))
+            return fail(SW_ERR_UNSUPPORTED, "no two-step tile shape at this order");
+    }
     if (d.pf < 0 || d.pf > 2) return fail(SW_ERR_ARG, "pf must be 0, 1 or 2");
     if (d.wt && p->prob.scheme != SW_CONST) return fail(SW_ERR_UNSUPPORTED, "wave tiles cover constant density");
     if (d.tx || d.nw) {
@@ -309,6 +391,7 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
     p->tile_nt = d.nt < 0 ? -1 : (d.nt ? 1 : 0);
     p->tile_pf = d.pf;
     p->tile_wt = d.wt ? 1 : 0;
+    p->tile_ts = d.ts;
     if (p->graph_exec) {
         (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
         p->graph_exec = nullptr;
@@ -321,7 +404,7 @@ sw_status sw_plan_get_tiling(const sw_plan *p, sw_tiling *out)
     set_error("");
     if (!p || !out) return fail(SW_ERR_ARG, "NULL argument");
     const Tiling t = choose_tiling(p);
-    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt};
+    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt, t.ts};
     return SW_OK;
 }
 
@@ -473,35 +556,71 @@ static sw_status enqueue_forward(sw_plan *p, const sw_fwd_io *io, hipStream_t s)
     auto release = [&]() {
         for (auto &e : ev) (void)hipEventDestroy(e);
     };
-    for (int k = 0; k < io->nsteps_run; ++k) {
+    // checkpoint slot of step n: (p^n, p^{n-1})
+    auto checkpoint = [&](int n, const float *cur, const float *prv) -> hipError_t {
+        if (!io->ckpt || n % io->ckpt_every != 0) return hipSuccess;
+        float *slot = io->ckpt + size_t(n / io->ckpt_every) * 2 * p->field_elems;
+        hipError_t e = launch_copy(slot, cur, p->field_elems, s);
+        if (e == hipSuccess) e = launch_copy(slot + p->field_elems, prv, p->field_elems, s);
+        return e;
+    };
+    // receivers and snapshot of step n, whose new level p^{n+1} is in f
+    auto outputs = [&](int n, const float *f) -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (rec.count) e = launch_record(rec, f, io->traces + size_t(n) * rec.count, s);
+        if (e == hipSuccess && io->snaps && io->saving_stride > 0 && (n + 1) % io->saving_stride == 0)
+            e = launch_snapshot(g, f, io->snaps + size_t((n + 1) / io->saving_stride - 1) * p->grid_nodes, s);
+        return e;
+    };
+    // span[k]: steps advanced by the launch bracketed by events 2k, 2k+1 (0: none)
+    std::vector<int> span(size_t(io->nsteps_run), 0);
+    const bool two = two_step_ready(p, io);
+    int k = 0;
+    while (k < io->nsteps_run) {
         const int n = io->step0 + k;
         float *cur = io->field[k % 2];
         float *nxt = io->field[(k + 1) % 2];
-        if (io->ckpt && n % io->ckpt_every == 0) {
-            float *slot = io->ckpt + size_t(n / io->ckpt_every) * 2 * p->field_elems;
-            SW_HIP(launch_copy(slot, cur, p->field_elems, s));
-            SW_HIP(launch_copy(slot + p->field_elems, nxt, p->field_elems, s));
+        if (two && io->nsteps_run - k >= 4) {
+            // four steps in two sweeps: (cur, nxt) -> field2 -> (cur, nxt)
+            float *t1 = io->field2[0], *t2 = io->field2[1];
+            const float *in[2][2] = {{cur, nxt}, {t2, t1}};
+            float *out[2][2] = {{t1, t2}, {nxt, cur}};
+            for (int h = 0; h < 2; ++h) {
+                const int m = n + 2 * h, km = k + 2 * h;
+                SW_HIP(checkpoint(m, in[h][0], in[h][1]));
+                if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * km], s));
+                SW_HIP(stencil_two(p, io, m, in[h][0], in[h][1], out[h][0], out[h][1], true, s));
+                if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * km + 1], s));
+                span[km] = 2;
+                SW_HIP(checkpoint(m + 1, out[h][0], in[h][0]));
+                SW_HIP(outputs(m, out[h][0]));
+                SW_HIP(outputs(m + 1, out[h][1]));
+            }
+            k += 4;
+            continue;
         }
+        SW_HIP(checkpoint(n, cur, nxt));
         P.cur = cur;
         P.nxt = nxt;
         if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * k], s));
         SW_HIP(stencil(p, MODE_FWD, P, s));
         if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * k + 1], s));
+        span[k] = 1;
         if (src.count) SW_HIP(launch_inject(src, nxt, nullptr, io->wavelet + size_t(n) * src.count, s));
-        if (rec.count) SW_HIP(launch_record(rec, nxt, io->traces + size_t(n) * rec.count, s));
-        if (io->snaps && io->saving_stride > 0 && (n + 1) % io->saving_stride == 0)
-            SW_HIP(launch_snapshot(g, nxt, io->snaps + size_t((n + 1) / io->saving_stride - 1) * p->grid_nodes, s));
+        SW_HIP(outputs(n, nxt));
+        ++k;
     }
     if (!ev.empty()) {
-        const hipError_t e = hipEventSynchronize(ev.back());
+        const hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             release();
-            return fail(SW_ERR_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+            return fail(SW_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
         }
-        for (int k = 0; k < io->nsteps_run; ++k) {
+        for (int j = 0; j < io->nsteps_run; ++j) {
+            if (span[j] == 0) continue;
             float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
-            io->stencil_ms[k] = ms;
+            (void)hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]);
+            for (int q = 0; q < span[j]; ++q) io->stencil_ms[j + q] = ms / span[j];
         }
     }
     release();
@@ -523,6 +642,10 @@ sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
     if (io->ckpt && io->ckpt_every <= 0) return fail(SW_ERR_ARG, "ckpt_every must be > 0");
     if (io->snaps && io->saving_stride < 0) return fail(SW_ERR_ARG, "saving_stride must be >= 0");
     if (io->stencil_ms && io->use_graph) return fail(SW_ERR_ARG, "stencil timing is not available with graphs");
+    if ((io->field2[0] || io->field2[1]) &&
+        (!io->field2[0] || !io->field2[1] || io->field2[0] == io->field2[1] || io->field2[0] == io->field[0] ||
+         io->field2[0] == io->field[1] || io->field2[1] == io->field[0] || io->field2[1] == io->field[1]))
+        return fail(SW_ERR_ARG, "field2 must be two more distinct wavefield buffers (or both NULL)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!io->use_graph) return enqueue_forward(p, io, s);
 
@@ -532,6 +655,7 @@ sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
     const std::vector<uint64_t> key = {
         uint64_t(uintptr_t(io->workspace)), uint64_t(uintptr_t(io->wavelet)),
         uint64_t(uintptr_t(io->field[0])), uint64_t(uintptr_t(io->field[1])),
+        uint64_t(uintptr_t(io->field2[0])), uint64_t(uintptr_t(io->field2[1])),
         uint64_t(uintptr_t(io->traces)), uint64_t(uintptr_t(io->snaps)), uint64_t(io->saving_stride),
         uint64_t(uintptr_t(io->ckpt)), uint64_t(io->ckpt_every), uint64_t(io->step0),
         uint64_t(io->nsteps_run)};

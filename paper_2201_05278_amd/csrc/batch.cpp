@@ -334,25 +334,29 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     auto it = cache.find(key);
     if (it != cache.end()) {
         auto &v = it->second;
-        const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"]};
+        const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"], v["ts"]};
         return sw_plan_set_tiling(p, &t);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    struct Shape { int tx, nw, wt; };
+    struct Shape { int tx, nw, wt, ts; };
     std::vector<Shape> shapes;
+    const bool two = p->ndim == 3 && p->prob.scheme == SW_CONST && io->field2[0] && io->field2[1];
     if (p->ndim == 3 && p->prob.scheme == SW_CONST)
-        shapes = {{16, 4, 0}, {8, 4, 0}, {32, 8, 0}, {16, 8, 0}, {8, 8, 0},
-                  {16, 4, 1}, {32, 4, 1}, {4, 1, 1}, {8, 1, 1}, {16, 2, 1}};
+        shapes = {{16, 4, 0, 1}, {8, 4, 0, 1}, {32, 8, 0, 1}, {16, 8, 0, 1}, {8, 8, 0, 1},
+                  {16, 4, 1, 1}, {32, 4, 1, 1}, {4, 1, 1, 1}, {8, 1, 1, 1}, {16, 2, 1, 1}};
     else if (p->ndim == 3)
-        shapes = {{16, 8, 0}, {8, 8, 0}, {8, 4, 0}, {16, 4, 0}};
+        shapes = {{16, 8, 0, 1}, {8, 8, 0, 1}, {8, 4, 0, 1}, {16, 4, 0, 1}};
     else
-        shapes = {{0, 0, 0}};
+        shapes = {{0, 0, 0, 1}};
+    if (two)
+        for (const auto &sh : std::vector<Shape>{{8, 4, 0, 2}, {16, 8, 0, 2}, {8, 8, 0, 2}, {16, 4, 0, 2}})
+            if (tb_shape_ok(p->r, sh.tx, sh.nw)) shapes.push_back(sh);
     const bool const3 = p->prob.scheme == SW_CONST;
     hipEvent_t e0, e1;
     SW_HIP(hipEventCreate(&e0));
     SW_HIP(hipEventCreate(&e1));
     float best = std::numeric_limits<float>::max();
-    sw_tiling best_t{0, 0, 0, -1, 0, 0};
+    sw_tiling best_t{0, 0, 0, -1, 0, 0, 0};
     StencilParams P;
     fill_params(p, io->workspace, P);
     P.cur = io->field[0];
@@ -361,17 +365,24 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
         for (int zc : zc_candidates(p->dims[0], p->r))
             for (int nt : {0, 1})
                 for (int pf : {1, 2}) {
-                if ((!const3 || sh.wt) && pf == 2) continue;
-                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt};
+                if ((!const3 || sh.wt || sh.ts == 2) && pf == 2) continue;
+                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts};
                 st = sw_plan_set_tiling(p, &cand);
                 if (st != SW_OK) continue;
-                for (int w = 0; w < 2; ++w) SW_HIP(stencil(p, MODE_FWD, P, s));
+                // per-step time: single sweeps, or two-step sweeps over half as many launches
+                auto run = [&]() -> hipError_t {
+                    if (sh.ts == 2)
+                        return stencil_two(p, io, 0, io->field[0], io->field[1], io->field2[0], io->field2[1],
+                                           false, s);
+                    return stencil(p, MODE_FWD, P, s);
+                };
+                for (int w = 0; w < 2; ++w) SW_HIP(run());
                 SW_HIP(hipEventRecord(e0, s));
                 const int reps = 5;
-                for (int k = 0; k < reps; ++k) SW_HIP(stencil(p, MODE_FWD, P, s));
+                for (int k = 0; k < reps; ++k) SW_HIP(run());
                 SW_HIP(hipEventRecord(e1, s));
                 SW_HIP(hipEventSynchronize(e1));
-                const float ms = elapsed(e0, e1) / reps;
+                const float ms = elapsed(e0, e1) / reps / sh.ts;
                 if (ms < best) {
                     best = ms;
                     best_t = cand;
@@ -382,7 +393,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     st = sw_plan_set_tiling(p, &best_t);
     if (st != SW_OK) return st;
     cache[key] = {{"tx", best_t.tx}, {"nw", best_t.nw}, {"zc", best_t.zc}, {"nt", best_t.nt},
-                  {"pf", best_t.pf}, {"wt", best_t.wt}};
+                  {"pf", best_t.pf}, {"wt", best_t.wt}, {"ts", best_t.ts}};
     write_cache(cache_path, cache);
     return SW_OK;
 }

@@ -41,6 +41,7 @@ struct StencilParams {
     const float *K;         // multiplier of (L p): dt^2 c^2, or dt^2 rho c^2
     const float *aux;       // b = 1/rho (staggered) or rho (centred); unused otherwise
     const float2 *damp;     // (A, B) by squared layer distance
+    int ndamp;              // entries of damp
     float *store;           // MODE_STORE: K (L p) written; MODE_IMAGE: read
     float *grad;            // MODE_IMAGE: += p * store / K^2
     Geom g;
@@ -59,9 +60,24 @@ struct Tiling {
     int nt;                 // 1: non-temporal loads/stores for the streamed arrays
     int pf;                 // planes of loads kept in flight ahead of the update (1 or 2)
     int wt;                 // 1: wave tiles (each wave owns tx / nw rows, no block barrier)
+    int ts;                 // time steps per sweep (1, or 2 for the two-step constant-density sweep)
+};
+
+// Second output and injection of a two-step sweep (P.cur = p^n, P.nxt = p^{n-1}
+// read only): p^{n+1} -> out1, p^{n+2} -> out2; inj[which * nuniq + u] is added
+// to node unode[u] after step n + which; box = inclusive (z, x, y) bounds of
+// the injection nodes (empty when nuniq == 0).
+struct TwoStepParams {
+    float *out1;
+    float *out2;
+    const int64_t *unode;
+    const float *inj;
+    int nuniq;
+    int box[6];
 };
 
 hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);
+hipError_t launch_const_two(int r, const Tiling &t, StencilParams &P, const TwoStepParams &T, hipStream_t s);
 hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
 
 // ---- point and utility kernels ----
@@ -109,6 +125,10 @@ hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const f
                              double dt, double inv_dv, hipStream_t s);
 hipError_t launch_inject(const PointTableDev &t, float *field, float *store, const float *amp,
                          hipStream_t s);
+// The values launch_inject would add, for two consecutive steps:
+// out[u] (amplitudes amp0) and out[nuniq + u] (amplitudes amp1).
+hipError_t launch_inject_values(const PointTableDev &t, const float *amp0, const float *amp1, float *out,
+                                hipStream_t s);
 hipError_t launch_record(const PointTableDev &t, const float *field, float *out, hipStream_t s);
 hipError_t launch_snapshot(const Geom &g, const float *field, float *out, hipStream_t s);
 // Fold dJ/dM from the extended grid onto the physical grid and scale by

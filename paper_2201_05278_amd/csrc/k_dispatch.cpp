@@ -28,6 +28,15 @@ hipError_t launch_const_r8(int, int, const Tiling &, StencilParams &, hipStream_
 hipError_t launch_batch_r8(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
 hipError_t launch_vd_r8(int, int, const Tiling &, StencilParams &, hipStream_t);
 
+hipError_t launch_tb_r1(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r2(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r3(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r4(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r5(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r6(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r7(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+hipError_t launch_tb_r8(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
+
 hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {
     switch (r) {
@@ -55,6 +64,21 @@ hipError_t launch_const_batch(int r, int ndim, const Tiling &t, const StencilPar
     case 6: return launch_batch_r6(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
     case 7: return launch_batch_r7(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
     case 8: return launch_batch_r8(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_const_two(int r, const Tiling &t, StencilParams &P, const TwoStepParams &T, hipStream_t s)
+{
+    switch (r) {
+    case 1: return launch_tb_r1(t, P, T, s);
+    case 2: return launch_tb_r2(t, P, T, s);
+    case 3: return launch_tb_r3(t, P, T, s);
+    case 4: return launch_tb_r4(t, P, T, s);
+    case 5: return launch_tb_r5(t, P, T, s);
+    case 6: return launch_tb_r6(t, P, T, s);
+    case 7: return launch_tb_r7(t, P, T, s);
+    case 8: return launch_tb_r8(t, P, T, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -98,8 +98,8 @@ __global__ void __launch_bounds__(kBlock) k_inject(PointTableDev t, float *__res
         for (int k = t.uptr[u] + sub; k < t.uptr[u + 1]; k += G) {
             const int e = t.uent[k];
             const float s = amp[t.pid[e]];
-            sa += t.coef_a[e] * s;
-            ss += t.coef_s[e] * s;
+            sa = fmaf(t.coef_a[e], s, sa);
+            ss = fmaf(t.coef_s[e], s, ss);
         }
     }
     sa = group_sum<G>(sa);
@@ -109,6 +109,25 @@ __global__ void __launch_bounds__(kBlock) k_inject(PointTableDev t, float *__res
         field[n] += sa;
         if (store) store[n] += ss;
     }
+}
+
+// The sums k_inject adds, for the amplitudes of two steps (blockIdx.y).
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_inject_values(PointTableDev t, const float *__restrict__ amp0,
+                                                          const float *__restrict__ amp1,
+                                                          float *__restrict__ out)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = gid / G, sub = gid % G;
+    const float *amp = blockIdx.y ? amp1 : amp0;
+    float sa = 0.0f;
+    if (u < t.nuniq)
+        for (int k = t.uptr[u] + sub; k < t.uptr[u + 1]; k += G) {
+            const int e = t.uent[k];
+            sa = fmaf(t.coef_a[e], amp[t.pid[e]], sa);
+        }
+    sa = group_sum<G>(sa);
+    if (u < t.nuniq && sub == 0) out[blockIdx.y * t.nuniq + u] = sa;
 }
 
 template <int G>
@@ -138,7 +157,7 @@ __global__ void __launch_bounds__(kBlock) k_inject_batch(const ShotPoints *__res
     if (u < t.nuniq)
         for (int k = t.uptr[u] + sub; k < t.uptr[u + 1]; k += G) {
             const int e = t.uent[k];
-            sa += t.coef_a[e] * amp[t.pid[e]];
+            sa = fmaf(t.coef_a[e], amp[t.pid[e]], sa);
         }
     sa = group_sum<G>(sa);
     if (u < t.nuniq && sub == 0) S.field[parity ^ 1][t.unode[u]] += sa;
@@ -309,6 +328,15 @@ hipError_t launch_record(const PointTableDev &t, const float *field, float *out,
     case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(blocks_exact(int64_t(N) * 32), NY), dim3(kBlock), 0, __VA_ARGS__); break; \
     default: hipLaunchKernelGGL(KERNEL<64>, dim3(blocks_exact(int64_t(N) * 64), NY), dim3(kBlock), 0, __VA_ARGS__); break; \
     }
+
+hipError_t launch_inject_values(const PointTableDev &t, const float *amp0, const float *amp1, float *out,
+                                hipStream_t s)
+{
+    if (t.nuniq <= 0) return hipSuccess;
+    const int G = group_size(t.max_per_node);
+    SW_GROUP_DISPATCH2(G, k_inject_values, t.nuniq, 2, s, t, amp0, amp1, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_inject_batch(const ShotPoints *shots, int nshots, int max_uniq, int max_per_node,
                                int step, int parity, hipStream_t s)

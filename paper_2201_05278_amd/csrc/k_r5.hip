@@ -1,6 +1,7 @@
 // Stencil kernels instantiated for radius 5 (space order 10).
 #include "stencil_const.h"
 #include "stencil_vd.h"
+#include "stencil_tb.h"
 
 namespace sw {
 
@@ -13,6 +14,11 @@ hipError_t launch_batch_r5(int ndim, const Tiling &t, const StencilParams *shots
                             int nshots, int parity, int nblocks, hipStream_t s)
 {
     return launch_batch_radius<5>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+}
+
+hipError_t launch_tb_r5(const Tiling &t, StencilParams &P, const TwoStepParams &T, hipStream_t s)
+{
+    return launch_tb_radius<5>(t, P, T, s);
 }
 
 hipError_t launch_vd_r5(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)

@@ -1,6 +1,7 @@
 // Stencil kernels instantiated for radius 6 (space order 12).
 #include "stencil_const.h"
 #include "stencil_vd.h"
+#include "stencil_tb.h"
 
 namespace sw {
 
@@ -13,6 +14,11 @@ hipError_t launch_batch_r6(int ndim, const Tiling &t, const StencilParams *shots
                             int nshots, int parity, int nblocks, hipStream_t s)
 {
     return launch_batch_radius<6>(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+}
+
+hipError_t launch_tb_r6(const Tiling &t, StencilParams &P, const TwoStepParams &T, hipStream_t s)
+{
+    return launch_tb_radius<6>(t, P, T, s);
 }
 
 hipError_t launch_vd_r6(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)

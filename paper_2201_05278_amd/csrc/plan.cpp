@@ -162,6 +162,7 @@ void build_workspace_map(sw_plan *p)
         o.coef_a = take(ne * sizeof(float));
         o.coef_s = take(ne * sizeof(float));
         o.wscaled = take(ne * sizeof(float));
+        o.inj = take(2 * nu * sizeof(float));
     };
     pts(p->src, w.src);
     pts(p->rec, w.rec);

@@ -50,6 +50,7 @@ struct WorkspaceMap {
         size_t coef_a = 0;   // float[nent]: A M w (/dV for sources): injection
         size_t coef_s = 0;   // float[nent]: M w / dV: source term of stored M (L u + Q s)
         size_t wscaled = 0;  // float[nent]: w / dV (sources) or w (receivers): recording
+        size_t inj = 0;      // float[2][nuniq]: injected values of the two steps of a sweep
     } src, rec;
     size_t total = 0;
 };
@@ -86,7 +87,7 @@ struct sw_plan {
     bool prepared = false;
     void *prepared_ws = nullptr;
     // stencil tiling chosen by sw_plan_set_tiling / sw_plan_autotune (tx == 0: default)
-    int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = -1, tile_pf = 0, tile_wt = 0;
+    int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = -1, tile_pf = 0, tile_wt = 0, tile_ts = 0;
     // cached HIP graph of a forward run, captured on a private stream
     void *graph_exec = nullptr;
     void *capture_stream = nullptr;

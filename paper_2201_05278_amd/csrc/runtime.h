@@ -28,11 +28,17 @@ PointTableDev table_dev(const sw_plan *p, const PointSet &ps, const WorkspaceMap
 bool const_shape_ok(int tx, int nw);
 bool vd_shape_ok(int tx, int nw);
 bool wave_shape_ok(int tx, int nw);
-int default_zc(const sw_plan *p, int tx, int64_t want);
+int default_zc(const sw_plan *p, int tx, int64_t want, int ts = 1);
 Tiling choose_tiling(const sw_plan *p);
 void fill_params(const sw_plan *p, void *ws, StencilParams &P);
 void set_tiles(const sw_plan *p, const Tiling &t, StencilParams &P);
 hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s);
+bool tb_shape_ok(int r, int tx, int nw);
+bool two_step_ready(const sw_plan *p, const sw_fwd_io *io);
+// One two-step sweep from (cur = p^n, prv = p^{n-1}) to out1 = p^{n+1},
+// out2 = p^{n+2}, with the sources of steps n and n+1 if `sources`.
+hipError_t stencil_two(const sw_plan *p, const sw_fwd_io *io, int n, const float *cur, const float *prv,
+                       float *out1, float *out2, bool sources, hipStream_t s);
 sw_status check_prepared(const sw_plan *p, void *ws);
 
 }  // namespace sw

@@ -43,12 +43,58 @@ __device__ __forceinline__ void st_stream(float v, float *p)
     else *p = v;
 }
 
+// The leapfrog update A (2 c + K lap) - B prev with its rounding pinned by
+// explicit fused multiply-adds, so that every kernel that evaluates it (block
+// tiles, wave tiles, batches, two-step sweeps) produces the same bits.
+__device__ __forceinline__ float leapfrog(float a, float b, float k, float lap, float c, float prev)
+{
+    return fmaf(a, fmaf(k, lap, 2.0f * c), -(b * prev));
+}
+
+// Buffer addressing: a resource descriptor (base, byte size) per array and
+// per z window, a per-thread 32-bit byte offset inside a plane and a uniform
+// (scalar) byte offset of the plane, so that a load costs no vector address
+// arithmetic.  Reads past the descriptor's size return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_res(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes), 0x00020000);
+}
+
+template <int NT>
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, NT ? 2 : 0));
+}
+
+template <int NT>
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, NT ? 2 : 0);
+}
+
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, int voff)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+}
+
+// Register-queue length of the block tile: at least 2R + 1 planes, rounded
+// up to a multiple of the slot and LDS-buffer periods so that a fully
+// unrolled round of Q planes addresses every queue entry, load slot and LDS
+// buffer with compile-time indices (no register moves).
+template <int R, int PF>
+constexpr int queue_len()
+{
+    constexpr int period = (PF + 1) % 2 == 0 ? PF + 1 : 2 * (PF + 1);
+    return (2 * R + 1 + period - 1) / period * period;
+}
+
 // One tile (TX x 64 columns, one z chunk) of one grid; `bid` is the tile's
 // index in (z chunk, x tile, y tile) order.
 template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
 __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
 {
     static_assert(TX % NW == 0, "rows must split evenly over waves");
+    static_assert(PF == 1 || PF == 2, "one or two planes of loads in flight");
     constexpr int RPT = TX / NW;                 // rows per thread
     constexpr int HXR = (NDIM == 3) ? R : 0;     // LDS halo rows in x
     constexpr int LY = 64 + 2 * R;
@@ -56,7 +102,9 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     constexpr int NTH = 64 * NW;
     constexpr int HXN = (NDIM == 3) ? (2 * R + NW - 1) / NW : 0;   // x-halo rows per wave
     constexpr int YHN = (TX * 2 * R + NTH - 1) / NTH;               // y-halo items per thread
-    __shared__ float lds[2][LX][LY];
+    constexpr int NS = PF + 1;                   // load slots
+    constexpr int Q = queue_len<R, PF>();
+    __shared__ float lds[2][LX + 1][LY];          // row LX: sink for idle halo lanes
 
     const Geom &g = P.g;
     const int lane = threadIdx.x & 63;
@@ -73,38 +121,51 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     const int64_t sz = int64_t(g.px) * g.py;
     const bool yin = y < g.Y;
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
-    // lane offsets inside a z plane: off(x, y) = xy0 + x py + y >= 0
-    auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
-    const float *cur0 = P.cur + g.base;
-    float *nxt0 = P.nxt + g.base;
-    const float *k0 = P.K + g.base;
+    // z window of this chunk: planes zw .. zt - 1, plane z at byte offset (z - zw) * pb
+    const int zw = max(zb - R, 0);
+    const int zt = min(ze + R, g.Z);
+    const int pb = int(sz) * 4;
+    const uint32_t wbytes = uint32_t(zt - zw) * uint32_t(pb);
+    const int64_t w0 = g.base + int64_t(zw) * sz;
+    const auto rc = buf_res(P.cur + w0, wbytes);
+    const auto rn = buf_res(P.nxt + w0, wbytes);
+    const auto rk = buf_res(P.K + w0, wbytes);
+    const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
+    __amdgpu_buffer_rsrc_t rs = rk, rg = rk;
+    if constexpr (MODE != MODE_FWD) rs = buf_res(P.store + w0, wbytes);
+    if constexpr (MODE == MODE_IMAGE) rg = buf_res(P.grad + w0, wbytes);
+    // byte offset of plane z in the window (planes below it clamp to its first plane)
+    auto soff = [&](int z) -> int { return max(z - zw, 0) * pb; };
+    // keep a loaded value (mask ~0) or replace it by +0 (mask 0)
+    auto keep = [](float v, unsigned m) -> float { return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m); };
+    // in-plane byte offsets: (xy0 + x py + y) * 4; nodes outside the grid get an
+    // offset past every window, so their loads read zero and their stores are dropped
+    auto off = [&](int x, int yy) -> int { return (g.xy0 + x * g.py + yy) * 4; };
+    constexpr int kOut = 0x7ffffe00;
 
-    unsigned ro[RPT];
+    int ro[RPT], ex2[RPT];
     bool rin[RPT];
-    int ex2[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         rin[i] = yin && x < g.X;
-        ro[i] = off(x, y);
+        ro[i] = rin[i] ? off(x, y) : kOut;
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
-        ex2[i] = ex * ex + ey * ey;
+        ex2[i] = rin[i] ? ex * ex + ey * ey : 0;      // keeps table reads in range
     }
-    unsigned hxo[HXN > 0 ? HXN : 1];
+    int hxo[HXN > 0 ? HXN : 1], hxrow[HXN > 0 ? HXN : 1];
     bool hxin[HXN > 0 ? HXN : 1], hxok[HXN > 0 ? HXN : 1];
-    int hxrow[HXN > 0 ? HXN : 1];
 #pragma unroll
     for (int s = 0; s < HXN; ++s) {
         const int hr = wave + s * NW;
         hxok[s] = hr < 2 * R;
         const int x = (hr < R) ? x0 - R + hr : x0 + TX + hr - R;
         hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
-        hxrow[s] = (hr < R) ? hr : TX + hr;
-        hxo[s] = hxin[s] ? off(x, y) : 0u;
+        hxrow[s] = !hxok[s] ? LX : (hr < R) ? hr : TX + hr;
+        hxo[s] = hxin[s] ? off(x, y) : kOut;
     }
-    unsigned hyo[YHN];
+    int hyo[YHN], hyrow[YHN], hycol[YHN];
     bool hyin[YHN], hyok[YHN];
-    int hyrow[YHN], hycol[YHN];
 #pragma unroll
     for (int s = 0; s < YHN; ++s) {
         const int e = threadIdx.x + s * NTH;
@@ -113,117 +174,94 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         const int yy = (c < R) ? y0 - R + c : y0 + 64 + c - R;
         const int x = x0 + row;
         hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
-        hyrow[s] = HXR + row;
+        hyrow[s] = hyok[s] ? HXR + row : LX;
         hycol[s] = (c < R) ? c : 64 + c;
-        hyo[s] = hyin[s] ? off(x, yy) : 0u;
+        hyo[s] = hyin[s] ? off(x, yy) : kOut;
     }
 
-    float q[RPT][2 * R + 1];
+    // q[i][(u + k) % Q] = p^n at plane z - R + k (k = 0 .. 2R) in unrolled step u
+    float q[RPT][Q];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
         const int z = zb - R + k;
-        const bool zin = z >= 0 && z < g.Z;
-        const float *pl = cur0 + int64_t(z) * sz;
+        const unsigned zm = (z >= 0 && z < g.Z) ? ~0u : 0u;
+        const int so = soff(min(z, zt - 1));
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) q[i][k] = (rin[i] && zin) ? pl[ro[i]] : 0.0f;
+        for (int i = 0; i < RPT; ++i) q[i][k] = keep(buf_ld<0>(rc, ro[i], so), zm);
     }
 
-    // loads for a plane, issued PF planes ahead of its use
     struct Slot {
-        float f[RPT], p[RPT], k[RPT], a[RPT], b[RPT], d[RPT], g[RPT];
+        float f[RPT], p[RPT], k[RPT], d[RPT], g[RPT];
+        float2 ab[RPT];
         float hx[HXN > 0 ? HXN : 1], hy[YHN];
     };
-    auto load = [&](int z, Slot &S) {
+    Slot S[NS];
+    auto load = [&](int z, Slot &T) {
         const int zf = z + R;
+        const unsigned fm = zf < g.Z ? ~0u : 0u;
+        const int so = soff(z), sf = soff(min(zf, zt - 1));
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
-        const float *pc = cur0 + int64_t(z) * sz;
-        const float *pf = cur0 + int64_t(zf) * sz;
-        const float *pn = nxt0 + int64_t(z) * sz;
-        const float *pk = k0 + int64_t(z) * sz;
-        const bool fin = zf < g.Z;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            S.f[i] = (rin[i] && fin) ? pf[ro[i]] : 0.0f;
-            S.p[i] = rin[i] ? ld_stream<NT>(pn + ro[i]) : 0.0f;
-            S.k[i] = rin[i] ? ld_stream<NT>(pk + ro[i]) : 0.0f;
-            const int d2 = ez * ez + ex2[i];
-            S.a[i] = 1.0f;
-            S.b[i] = 1.0f;
-            if (rin[i] && d2 > 0) {
-                const float2 ab = P.damp[d2];
-                S.a[i] = ab.x;
-                S.b[i] = ab.y;
-            }
+            T.f[i] = keep(buf_ld<0>(rc, ro[i], sf), fm);
+            T.p[i] = buf_ld<NT>(rn, ro[i], so);
+            T.k[i] = buf_ld<NT>(rk, ro[i], so);
+            // (A, B) by squared layer distance; entry 0 is (1, 1)
+            T.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
             if constexpr (MODE == MODE_IMAGE) {
-                const int64_t o = int64_t(z) * sz + g.base + ro[i];
-                S.d[i] = rin[i] ? ld_stream<NT>(P.store + o) : 0.0f;
-                S.g[i] = rin[i] ? ld_stream<NT>(P.grad + o) : 0.0f;
+                T.d[i] = buf_ld<NT>(rs, ro[i], so);
+                T.g[i] = buf_ld<NT>(rg, ro[i], so);
             }
         }
 #pragma unroll
-        for (int s = 0; s < HXN; ++s) S.hx[s] = hxin[s] ? pc[hxo[s]] : 0.0f;
+        for (int s = 0; s < HXN; ++s) T.hx[s] = buf_ld<0>(rc, hxo[s], so);
 #pragma unroll
-        for (int s = 0; s < YHN; ++s) S.hy[s] = hyin[s] ? pc[hyo[s]] : 0.0f;
+        for (int s = 0; s < YHN; ++s) T.hy[s] = buf_ld<0>(rc, hyo[s], so);
     };
 
-    // consume the slot of plane z (then refill it for plane z + PF) and update plane z
-    auto plane = [&](int z, Slot &S, float (*T)[LY]) {
-        const Slot W = S;
-        if (z + PF < ze) load(z + PF, S);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) q[i][2 * R] = W.f[i];
+    for (int j = 0; j < PF; ++j)
+        if (zb + j < ze) load(zb + j, S[j]);
+    for (int zz = zb; zz < ze; zz += Q) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) T[HXR + wave * RPT + i][R + lane] = q[i][R];
+        for (int u = 0; u < Q; ++u) {
+            const int z = zz + u;
+            if (z < ze) {
+                Slot &W = S[u % NS];
+                if (z + PF < ze) load(z + PF, S[(u + PF) % NS]);
+                float(*T)[LY] = lds[u % 2];
 #pragma unroll
-        for (int s = 0; s < HXN; ++s)
-            if (hxok[s]) T[hxrow[s]][R + lane] = W.hx[s];
+                for (int i = 0; i < RPT; ++i) q[i][(u + 2 * R) % Q] = W.f[i];
 #pragma unroll
-        for (int s = 0; s < YHN; ++s)
-            if (hyok[s]) T[hyrow[s]][hycol[s]] = W.hy[s];
-        __syncthreads();
+                for (int i = 0; i < RPT; ++i) T[HXR + wave * RPT + i][R + lane] = q[i][(u + R) % Q];
+#pragma unroll
+                for (int s = 0; s < HXN; ++s) T[hxrow[s]][R + lane] = W.hx[s];
+#pragma unroll
+                for (int s = 0; s < YHN; ++s) T[hyrow[s]][hycol[s]] = W.hy[s];
+                __syncthreads();
 
-        float *pn = nxt0 + int64_t(z) * sz;
+                const int so = soff(z);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int lx = HXR + wave * RPT + i, ly = R + lane;
-            const float c = q[i][R];
-            float lap = P.c0 * c;
+                for (int i = 0; i < RPT; ++i) {
+                    const int lx = HXR + wave * RPT + i, ly = R + lane;
+                    const float c = q[i][(u + R) % Q];
+                    float lap = P.c0 * c;
 #pragma unroll
-            for (int j = 1; j <= R; ++j) lap = fmaf(P.cz[j], q[i][R + j] + q[i][R - j], lap);
-            if constexpr (NDIM == 3) {
+                    for (int j = 1; j <= R; ++j)
+                        lap = fmaf(P.cz[j], q[i][(u + R + j) % Q] + q[i][(u + R - j) % Q], lap);
+                    if constexpr (NDIM == 3) {
 #pragma unroll
-                for (int j = 1; j <= R; ++j) lap = fmaf(P.cx[j], T[lx + j][ly] + T[lx - j][ly], lap);
+                        for (int j = 1; j <= R; ++j) lap = fmaf(P.cx[j], T[lx + j][ly] + T[lx - j][ly], lap);
+                    }
+#pragma unroll
+                    for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[lx][ly + j] + T[lx][ly - j], lap);
+                    const float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, c, W.p[i]);
+                    buf_st<NT>(out, rn, ro[i], so);
+                    if constexpr (MODE == MODE_STORE) buf_st<NT>(W.k[i] * lap, rs, ro[i], so);
+                    if constexpr (MODE == MODE_IMAGE)
+                        buf_st<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), rg, ro[i], so);
+                }
             }
-#pragma unroll
-            for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[lx][ly + j] + T[lx][ly - j], lap);
-            const float out = W.a[i] * fmaf(W.k[i], lap, 2.0f * c) - W.b[i] * W.p[i];
-            if (rin[i]) {
-                st_stream<NT>(out, pn + ro[i]);
-                const int64_t o = int64_t(z) * sz + g.base + ro[i];
-                if constexpr (MODE == MODE_STORE) st_stream<NT>(W.k[i] * lap, P.store + o);
-                if constexpr (MODE == MODE_IMAGE)
-                    st_stream<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), P.grad + o);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < RPT; ++i)
-#pragma unroll
-            for (int k = 0; k < 2 * R; ++k) q[i][k] = q[i][k + 1];
-    };
-
-    Slot s0, s1;
-    load(zb, s0);
-    if constexpr (PF == 2) {
-        if (zb + 1 < ze) load(zb + 1, s1);
-        for (int z = zb; z < ze; z += 2) {
-            plane(z, s0, lds[0]);
-            if (z + 1 < ze) plane(z + 1, s1, lds[1]);
-        }
-    } else {
-        int buf = 0;
-        for (int z = zb; z < ze; ++z) {
-            plane(z, s0, lds[buf]);
-            buf ^= 1;
         }
     }
 }
@@ -388,7 +426,7 @@ __device__ __forceinline__ void const_wave_tile(const StencilParams &P, int bid)
             }
 #pragma unroll
             for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[i][R + lane + j] + T[i][R + lane - j], lap);
-            const float out = W.a[i] * fmaf(W.k[i], lap, 2.0f * c) - W.b[i] * W.p[i];
+            const float out = leapfrog(W.a[i], W.b[i], W.k[i], lap, c, W.p[i]);
             if (rin[i]) {
                 st_stream<NT>(out, pn + ro[i]);
                 const int64_t o = int64_t(z) * sz + g.base + ro[i];

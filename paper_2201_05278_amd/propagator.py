@@ -184,10 +184,10 @@ class Propagator:
         return self
 
     # ---- tiling -------------------------------------------------------------
-    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0):
-        """Stencil tile shape, z-chunk length, cache policy, prefetch distance
-        and wave-tile mode (0 / -1: default)."""
-        t = L.Tiling(tx, nw, zc, nt, pf, wt)
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0, ts=0):
+        """Stencil tile shape, z-chunk length, cache policy, prefetch distance,
+        wave-tile mode and time steps per sweep (0 / -1: default)."""
+        t = L.Tiling(tx, nw, zc, nt, pf, wt, ts)
         L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, ctypes.byref(t)))
 
     @property
@@ -203,8 +203,22 @@ class Propagator:
         io = L.FwdIO()
         io.workspace = _ptr(self.workspace).value
         io.field[0], io.field[1] = fields[0].data_ptr(), fields[1].data_ptr()
+        spare = self._spare_fields(force=True)
+        if spare is not None:
+            io.field2[0], io.field2[1] = spare[0].data_ptr(), spare[1].data_ptr()
         L.check("sw_plan_autotune", L.lib().sw_plan_autotune(
             self._plan, ctypes.byref(io), cache_path.encode() if cache_path else None, _stream()))
+
+    def _spare_fields(self, force=False):
+        """The two extra wavefield buffers of two-step sweeps (3D constant
+        density), allocated once when the tiling uses them (or force)."""
+        if self.ndim != 3 or self.scheme != "const":
+            return None
+        if not force and self.tiling["ts"] != 2:
+            return None
+        if getattr(self, "_field2", None) is None:
+            self._field2 = (self.new_field(), self.new_field())
+        return self._field2
 
     def _fwd_io(self, wavelet, fields, traces):
         lay = self.layout
@@ -255,6 +269,9 @@ class Propagator:
         if stencil_ms is not None:
             assert stencil_ms.dtype.name == "float32" and stencil_ms.size >= nrun
             io.stencil_ms = stencil_ms.ctypes.data_as(L.c_float_p)
+        spare = self._spare_fields()
+        if spare is not None:
+            io.field2[0], io.field2[1] = spare[0].data_ptr(), spare[1].data_ptr()
         self._keep = (wavelet, fields, traces, snaps, ckpt)
         L.check("sw_forward", L.lib().sw_forward(self._plan, ctypes.byref(io), _stream()))
         return ForwardResult(traces, fields, nrun % 2, snaps, ckpt, int(checkpoint_every))

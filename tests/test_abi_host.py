@@ -148,3 +148,27 @@ def test_forward_before_prepare_refused():
     io = L.FwdIO()
     st = L.lib().sw_forward(prop._plan, ctypes.byref(io), None)
     assert L.STATUS[st] == "SW_ERR_STATE"
+
+
+def test_tiling_choices_validated():
+    prop = Propagator((30, 30, 30), (10.0,) * 3, 8, 1e-3, 5, nbl=4)
+    prop.set_tiling(ts=2)
+    t = prop.tiling
+    assert (t["ts"], t["tx"], t["nw"], t["wt"]) == (2, 8, 4, 0)
+    prop.set_tiling(16, 8, ts=2)                 # 2 (5R+5) + 1 (3R+3) = 65 values fit at R = 4
+    _expect("SW_ERR_UNSUPPORTED", prop.set_tiling, 16, 4, ts=2)   # 4 (5R+5) + 2 (3R+3) = 130
+    _expect("SW_ERR_ARG", prop.set_tiling, ts=3)
+    _expect("SW_ERR_ARG", prop.set_tiling, 8, 1, wt=1, ts=2)
+    _expect("SW_ERR_UNSUPPORTED", prop.set_tiling, 32, 8, ts=2)
+    prop.set_tiling()
+    assert prop.tiling["ts"] in (1, 2)
+    so16 = Propagator((30, 30, 30), (10.0,) * 3, 16, 1e-4, 5, nbl=4)
+    _expect("SW_ERR_UNSUPPORTED", so16.set_tiling, 8, 4, ts=2)    # 2 * 45 + 4 * 27 > 95
+    _expect("SW_ERR_UNSUPPORTED", so16.set_tiling, 8, 8, ts=2)    # 45 + 2 * 27 > 95
+    _expect("SW_ERR_UNSUPPORTED", so16.set_tiling, ts=2)
+    so14 = Propagator((30, 30, 30), (10.0,) * 3, 14, 1e-4, 5, nbl=4)
+    so14.set_tiling(8, 8, ts=2)
+    flat = Propagator((30, 30), (10.0,) * 2, 8, 1e-3, 5, nbl=4)
+    _expect("SW_ERR_UNSUPPORTED", flat.set_tiling, ts=2)
+    vd = Propagator((30, 30, 30), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered", nbl=4)
+    _expect("SW_ERR_UNSUPPORTED", vd.set_tiling, ts=2)
