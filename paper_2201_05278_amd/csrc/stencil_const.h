@@ -143,6 +143,10 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     auto off = [&](int x, int yy) -> int { return (g.xy0 + x * g.py + yy) * 4; };
     constexpr int kOut = 0x7ffffe00;
 
+    // the tile lies inside the physical box along x and y: (A, B) = (1, 1) on
+    // every plane whose z is outside the layer, no table reads there
+    const bool inner_xy = x0 >= g.lo[1] && x0 + TX <= g.lo[1] + g.np[1] && y0 >= g.lo[2] &&
+                          y0 + 64 <= g.lo[2] + g.np[2];
     int ro[RPT], ex2[RPT];
     bool rin[RPT];
 #pragma unroll
@@ -201,13 +205,19 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         const unsigned fm = zf < g.Z ? ~0u : 0u;
         const int so = soff(z), sf = soff(min(zf, zt - 1));
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
+        // (A, B) by squared layer distance (entry 0 is (1, 1)); skipped on interior tile planes
+        if (!inner_xy || ez > 0) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) T.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) T.ab[i] = make_float2(1.0f, 1.0f);
+        }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             T.f[i] = keep(buf_ld<0>(rc, ro[i], sf), fm);
             T.p[i] = buf_ld<NT>(rn, ro[i], so);
             T.k[i] = buf_ld<NT>(rk, ro[i], so);
-            // (A, B) by squared layer distance; entry 0 is (1, 1)
-            T.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
             if constexpr (MODE == MODE_IMAGE) {
                 T.d[i] = buf_ld<NT>(rs, ro[i], so);
                 T.g[i] = buf_ld<NT>(rg, ro[i], so);

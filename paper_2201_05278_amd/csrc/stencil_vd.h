@@ -33,20 +33,28 @@ template <int R, int NDIM, int TX, int NW, int NT>
 __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
 {
     static_assert(TX % NW == 0, "rows must split evenly over waves");
+    static_assert(NDIM == 3 || TX == 1, "2D grids use one row per tile");
     constexpr int RPT = TX / NW;
-    constexpr int H2 = 2 * R;
-    constexpr int HX = (NDIM == 3) ? H2 : 0;
-    constexpr int LY = 64 + 2 * H2;
+    constexpr int H = 2 * R - 1;                  // node halo of the face fluxes
+    constexpr int HX = (NDIM == 3) ? H : 0;
+    constexpr int LY = 64 + 2 * H;
     constexpr int LX = TX + 2 * HX;
-    constexpr int FY = 64 + 2 * R;
+    constexpr int FX = (NDIM == 3) ? TX + 2 * R - 1 : 1;   // x faces x0-R+t+1/2, t < FX
+    constexpr int FY = 64 + 2 * R - 1;                     // y faces y0-R+c+1/2, c < FY
     constexpr int NTH = 64 * NW;
-    constexpr int NCOL = RPT + 4 * R - 2;
-    constexpr int NFX = RPT + 2 * R - 1;
-    constexpr int HXN = (NDIM == 3) ? (2 * HX + NW - 1) / NW : 0;
-    constexpr int YHN = (TX * 2 * H2 + NTH - 1) / NTH;
-    __shared__ float sp[LX][LY];
-    __shared__ float sb[LX][LY];
-    __shared__ float sfy[TX][FY];
+    constexpr int HXN = (NDIM == 3) ? (2 * HX + NW - 1) / NW : 0;   // x-halo rows per wave
+    constexpr int YHN = (TX * 2 * H + NTH - 1) / NTH;               // y-halo items per thread
+    constexpr int FXR = (NDIM == 3) ? FX : 0;     // x-face rows
+    // face items: rows of 64 (x faces, then the first 64 y faces of each tile
+    // row, wave aligned) and the last 2R - 1 y faces of each tile row
+    constexpr int NI = (FXR + TX) * 64 + TX * (2 * R - 1);
+    constexpr int NIT = (NI + NTH - 1) / NTH;     // face items per thread
+    constexpr int Q = 2 * R;                      // queue length (even: slots alternate)
+    constexpr int kOut = 0x7ffffe00;
+    __shared__ float sp[LX + 1][LY];              // last row: sink for idle items
+    __shared__ float sb[LX + 1][LY];
+    __shared__ float sfx[FX + 1][64];
+    __shared__ float sfy[TX + 1][FY];
 
     const Geom &g = P.g;
     const int lane = threadIdx.x & 63;
@@ -65,244 +73,222 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const bool yin = y < g.Y;
     const int yc = clampi(y, 0, g.Y - 1);
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
-    // plane base pointers + unsigned 32-bit lane offsets off(x, y) = xy0 + x py + y
-    auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
-    const float *cur = P.cur + g.base;
-    const float *bm = P.aux + g.base;
-    float *nxt = P.nxt + g.base;
-    const float *km = P.K + g.base;
+    // z window: planes zw .. zt - 1 (the queue reaches 2R - 1 planes ahead)
+    const int zw = max(zb - 2 * R + 1, 0);
+    const int zt = min(ze + 2 * R - 1, g.Z);
+    const int pb = int(sz) * 4;
+    const uint32_t wbytes = uint32_t(zt - zw) * uint32_t(pb);
+    const int64_t w0 = g.base + int64_t(zw) * sz;
+    const auto rc = buf_res(P.cur + w0, wbytes);
+    const auto rbm = buf_res(P.aux + w0, wbytes);
+    const auto rn = buf_res(P.nxt + w0, wbytes);
+    const auto rk = buf_res(P.K + w0, wbytes);
+    const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
+    auto soff = [&](int z) -> int { return (clampi(z, zw, zt - 1) - zw) * pb; };
+    auto keep = [](float v, unsigned m) -> float {
+        return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m);
+    };
+    // byte offsets in a plane: wavefield (zero off the grid) and model (nearest grid node)
+    auto off = [&](int x, int yy) -> int {
+        return (x >= 0 && x < g.X && yy >= 0 && yy < g.Y) ? (g.xy0 + x * g.py + yy) * 4 : kOut;
+    };
+    auto moff = [&](int x, int yy) -> int { return (g.xy0 + clampi(x, 0, g.X - 1) * g.py + clampi(yy, 0, g.Y - 1)) * 4; };
 
-    unsigned roff[RPT], rboff[RPT];
-    bool rin[RPT];
-    int ex2[RPT];
+    int ro[RPT], rm[RPT], ex2[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
-        rin[i] = yin && x < g.X;
-        roff[i] = rin[i] ? off(x, y) : 0u;
-        rboff[i] = off(clampi(x, 0, g.X - 1), yc);
+        const bool in = yin && x < g.X;
+        ro[i] = off(x, y);
+        rm[i] = moff(x, y);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
-        ex2[i] = ex * ex + ey * ey;
+        ex2[i] = in ? ex * ex + ey * ey : 0;
     }
-    // x-halo rows (3D): 2R rows on each side, one lane per column
-    unsigned hxo[HXN > 0 ? HXN : 1], hxbo[HXN > 0 ? HXN : 1];
-    bool hxin[HXN > 0 ? HXN : 1], hxok[HXN > 0 ? HXN : 1];
-    int hxrow[HXN > 0 ? HXN : 1];
+    int hxo[HXN > 0 ? HXN : 1], hxm[HXN > 0 ? HXN : 1], hxrow[HXN > 0 ? HXN : 1];
 #pragma unroll
     for (int s = 0; s < HXN; ++s) {
         const int hr = wave + s * NW;
-        hxok[s] = hr < 2 * HX;
+        const bool ok = hr < 2 * HX;
         const int x = (hr < HX) ? x0 - HX + hr : x0 + TX + hr - HX;
-        hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
-        hxrow[s] = (hr < HX) ? hr : TX + hr;
-        hxo[s] = hxin[s] ? off(x, y) : 0u;
-        hxbo[s] = off(clampi(x, 0, g.X - 1), yc);
+        hxo[s] = ok ? off(x, y) : kOut;
+        hxm[s] = moff(x, y);
+        hxrow[s] = !ok ? LX : (hr < HX) ? hr : TX + hr;
     }
-    // y-halo columns: 2R on each side of every tile row
-    unsigned hyo[YHN], hybo[YHN];
-    bool hyin[YHN], hyok[YHN];
-    int hyrow[YHN], hycol[YHN];
+    int hyo[YHN], hym[YHN], hyrow[YHN], hycol[YHN];
 #pragma unroll
     for (int s = 0; s < YHN; ++s) {
         const int e = threadIdx.x + s * NTH;
-        hyok[s] = e < TX * 2 * H2;
-        const int row = e / (2 * H2), c = e % (2 * H2);
-        const int yy = (c < H2) ? y0 - H2 + c : y0 + 64 + c - H2;
+        const bool ok = e < TX * 2 * H;
+        const int row = e / (2 * H), c = e % (2 * H);
+        const int yy = (c < H) ? y0 - H + c : y0 + 64 + c - H;
         const int x = x0 + row;
-        hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
-        hyrow[s] = HX + row;
-        hycol[s] = (c < H2) ? c : 64 + c;
-        hyo[s] = hyin[s] ? off(x, yy) : 0u;
-        hybo[s] = off(clampi(x, 0, g.X - 1), clampi(yy, 0, g.Y - 1));
+        hyo[s] = ok ? off(x, yy) : kOut;
+        hym[s] = moff(x, yy);
+        hyrow[s] = ok ? HX + row : LX;
+        hycol[s] = (c < H) ? c : 64 + c;
+    }
+    // face items of phase two: kind 0 x face (row t, lane column), 1 y face
+    // (tile row r, face column c), 2 idle (written to the sink rows)
+    int fk[NIT], fa[NIT], fc[NIT];
+#pragma unroll
+    for (int s = 0; s < NIT; ++s) {
+        const int e = threadIdx.x + s * NTH;
+        if (e < FXR * 64) {
+            fk[s] = 0; fa[s] = e / 64; fc[s] = e % 64;
+        } else if (e < (FXR + TX) * 64) {
+            fk[s] = 1; fa[s] = e / 64 - FXR; fc[s] = e % 64;
+        } else if (e < NI) {
+            const int t = e - (FXR + TX) * 64;
+            fk[s] = 1; fa[s] = t / (2 * R - 1); fc[s] = 64 + t % (2 * R - 1);
+        } else {
+            fk[s] = 2; fa[s] = TX; fc[s] = 0;
+        }
     }
 
-    auto pz_ = [&](int i, int z) -> float {
-        return (rin[i] && z >= 0 && z < g.Z) ? (cur + int64_t(z) * sz)[roff[i]] : 0.0f;
-    };
-    auto bz_ = [&](int i, int z) -> float {
-        return (bm + int64_t(clampi(z, 0, g.Z - 1)) * sz)[rboff[i]];
-    };
-
-    // queues: pq[k] = p(z + k), bq[k] = b(z + k), fq[k] = z-flux at face (z - R + k) + 1/2
-    float pq[RPT][2 * R], bq[RPT][2 * R], fq[RPT][2 * R];
+    // queues, rotating with the unrolled step u: pq[(u + k) % Q] = p(z + k),
+    // bq[(u + k) % Q] = b(z + k), fq[(u + k) % Q] = z flux at face (z - R + k) + 1/2
+    float pq[RPT][Q], bq[RPT][Q], fq[RPT][Q];
     const int zs = zb - 2 * R + 1;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
+    for (int k = 0; k < 2 * R - 1; ++k) {
+        const int z = zs + k;
+        const unsigned m = (z >= 0 && z < g.Z) ? ~0u : 0u;
+        const int so = soff(z);
 #pragma unroll
-        for (int k = 0; k < 2 * R - 1; ++k) {
-            pq[i][k] = pz_(i, zs + k);
-            bq[i][k] = bz_(i, zs + k);
+        for (int i = 0; i < RPT; ++i) {
+            pq[i][k] = keep(buf_ld<0>(rc, ro[i], so), m);
+            bq[i][k] = buf_ld<0>(rbm, rm[i], so);
         }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
 #pragma unroll
         for (int k = 0; k < 2 * R; ++k) fq[i][k] = 0.0f;
-    }
 
-    float fp[RPT], fb[RPT], np_[RPT], nk[RPT], na[RPT], nb[RPT];
-    float nhxp[HXN > 0 ? HXN : 1], nhxb[HXN > 0 ? HXN : 1], nhyp[YHN], nhyb[YHN];
-    auto load = [&](int z) {
+    struct Slot {
+        float fp[RPT], fb[RPT], p[RPT], k[RPT];
+        float2 ab[RPT];
+        float hxp[HXN > 0 ? HXN : 1], hxb[HXN > 0 ? HXN : 1], hyp[YHN], hyb[YHN];
+    };
+    // loads of plane z: the queue input at z + 2R - 1, and for z >= zb the
+    // plane's own p^{n-1}, K, (A, B) and the halos of p and b
+    auto load = [&](int z, Slot &L) {
         const int zf = z + 2 * R - 1;
+        const unsigned mf = zf < g.Z ? ~0u : 0u;
+        const int sf = soff(zf);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            fp[i] = pz_(i, zf);
-            fb[i] = bz_(i, zf);
+            L.fp[i] = keep(buf_ld<0>(rc, ro[i], sf), mf);
+            L.fb[i] = buf_ld<0>(rbm, rm[i], sf);
         }
         if (z < zb) return;
+        const int so = soff(z);
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
-        const int64_t zo = int64_t(z) * sz;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            np_[i] = rin[i] ? ld_stream<NT>(nxt + zo + roff[i]) : 0.0f;
-            nk[i] = rin[i] ? ld_stream<NT>(km + zo + roff[i]) : 0.0f;
-            const int d2 = ez * ez + ex2[i];
-            na[i] = 1.0f;
-            nb[i] = 1.0f;
-            if (rin[i] && d2 > 0) {
-                const float2 ab = P.damp[d2];
-                na[i] = ab.x;
-                nb[i] = ab.y;
-            }
+            L.p[i] = buf_ld<NT>(rn, ro[i], so);
+            L.k[i] = buf_ld<NT>(rk, ro[i], so);
+            L.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
         }
 #pragma unroll
         for (int s = 0; s < HXN; ++s) {
-            nhxp[s] = hxin[s] ? (cur + zo)[hxo[s]] : 0.0f;
-            nhxb[s] = hxok[s] ? (bm + zo)[hxbo[s]] : 0.0f;
+            L.hxp[s] = buf_ld<0>(rc, hxo[s], so);
+            L.hxb[s] = buf_ld<0>(rbm, hxm[s], so);
         }
 #pragma unroll
         for (int s = 0; s < YHN; ++s) {
-            nhyp[s] = hyin[s] ? (cur + zo)[hyo[s]] : 0.0f;
-            nhyb[s] = hyok[s] ? (bm + zo)[hybo[s]] : 0.0f;
+            L.hyp[s] = buf_ld<0>(rc, hyo[s], so);
+            L.hyb[s] = buf_ld<0>(rbm, hym[s], so);
         }
     };
 
-    load(zs);
-    for (int z = zs; z < ze; ++z) {
-        const bool out_plane = z >= zb;
-        float pp[RPT], pk[RPT], pa[RPT], pb[RPT];
-        float hxp[HXN > 0 ? HXN : 1], hxb[HXN > 0 ? HXN : 1], hyp[YHN], hyb[YHN];
+    Slot S[2];
+    load(zs, S[0]);
+    for (int zz = zs; zz < ze; zz += Q) {
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+        const int z = zz + u;
+        if (z >= ze) break;
+        Slot &W = S[u % 2];
+        if (z + 1 < ze) load(z + 1, S[(u + 1) % 2]);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            pq[i][2 * R - 1] = fp[i];
-            bq[i][2 * R - 1] = fb[i];
-            pp[i] = np_[i];
-            pk[i] = nk[i];
-            pa[i] = na[i];
-            pb[i] = nb[i];
+            pq[i][(u + 2 * R - 1) % Q] = W.fp[i];
+            bq[i][(u + 2 * R - 1) % Q] = W.fb[i];
         }
-#pragma unroll
-        for (int s = 0; s < HXN; ++s) {
-            hxp[s] = nhxp[s];
-            hxb[s] = nhxb[s];
-        }
-#pragma unroll
-        for (int s = 0; s < YHN; ++s) {
-            hyp[s] = nhyp[s];
-            hyb[s] = nhyb[s];
-        }
-        if (z + 1 < ze) load(z + 1);
-
-        // new z-flux at face (z + R - 1) + 1/2
+        // z flux at face (z + R - 1) + 1/2
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             float bf = 0.0f, dp = 0.0f;
 #pragma unroll
             for (int l = 1; l <= R; ++l) {
-                bf = fmaf(P.mj[l], bq[i][R - 1 + l] + bq[i][R - l], bf);
-                dp = fmaf(P.sz[l], pq[i][R - 1 + l] - pq[i][R - l], dp);
+                bf = fmaf(P.mj[l], bq[i][(u + R - 1 + l) % Q] + bq[i][(u + R - l) % Q], bf);
+                dp = fmaf(P.sz[l], pq[i][(u + R - 1 + l) % Q] - pq[i][(u + R - l) % Q], dp);
             }
-            fq[i][2 * R - 1] = bf * dp;
+            fq[i][(u + 2 * R - 1) % Q] = bf * dp;
         }
 
-        if (out_plane) {
-            // phase 1: stage p and b of plane z
+        if (z >= zb) {
+            // phase one: stage p and b of plane z with an H-node halo
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                sp[HX + wave * RPT + i][H2 + lane] = pq[i][0];
-                sb[HX + wave * RPT + i][H2 + lane] = bq[i][0];
+                sp[HX + wave * RPT + i][H + lane] = pq[i][u % Q];
+                sb[HX + wave * RPT + i][H + lane] = bq[i][u % Q];
             }
 #pragma unroll
-            for (int s = 0; s < HXN; ++s)
-                if (hxok[s]) {
-                    sp[hxrow[s]][H2 + lane] = hxp[s];
-                    sb[hxrow[s]][H2 + lane] = hxb[s];
-                }
+            for (int s = 0; s < HXN; ++s) {
+                sp[hxrow[s]][H + lane] = W.hxp[s];
+                sb[hxrow[s]][H + lane] = W.hxb[s];
+            }
 #pragma unroll
-            for (int s = 0; s < YHN; ++s)
-                if (hyok[s]) {
-                    sp[hyrow[s]][hycol[s]] = hyp[s];
-                    sb[hyrow[s]][hycol[s]] = hyb[s];
-                }
+            for (int s = 0; s < YHN; ++s) {
+                sp[hyrow[s]][hycol[s]] = W.hyp[s];
+                sb[hyrow[s]][hycol[s]] = W.hyb[s];
+            }
             __syncthreads();
 
-            // phase 2: y-fluxes into LDS; x-fluxes and their differences per wave
-            float dx[RPT];
+            // phase two: every x and y face flux of the tile, once
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int lr = HX + wave * RPT + i;
-#pragma unroll
-                for (int rep = 0; rep < 2; ++rep) {
-                    const int k = lane + rep * 64;
-                    if (rep == 1 && lane >= 2 * R - 1) break;
-                    float bf = 0.0f, dp = 0.0f;
+            for (int s = 0; s < NIT; ++s) {
+                float bf = 0.0f, dp = 0.0f;
+                if (NDIM == 3 && fk[s] == 0) {
+                    const int t = fa[s], c = H + fc[s];
 #pragma unroll
                     for (int l = 1; l <= R; ++l) {
-                        bf = fmaf(P.mj[l], sb[lr][k + l + R] + sb[lr][k - l + 1 + R], bf);
-                        dp = fmaf(P.sy[l], sp[lr][k + l + R] - sp[lr][k - l + 1 + R], dp);
+                        bf = fmaf(P.mj[l], sb[t + R - 1 + l][c] + sb[t + R - l][c], bf);
+                        dp = fmaf(P.sx[l], sp[t + R - 1 + l][c] - sp[t + R - l][c], dp);
                     }
-                    sfy[wave * RPT + i][k] = bf * dp;
-                }
-                dx[i] = 0.0f;
-            }
-            if constexpr (NDIM == 3) {
-                float cp[NCOL], cb[NCOL], fx[NFX];
-#pragma unroll
-                for (int t = 0; t < NCOL; ++t) {
-                    cp[t] = sp[wave * RPT + 1 + t][H2 + lane];
-                    cb[t] = sb[wave * RPT + 1 + t][H2 + lane];
-                }
-#pragma unroll
-                for (int f = 0; f < NFX; ++f) {
-                    float bf = 0.0f, dp = 0.0f;
+                    sfx[t][fc[s]] = bf * dp;
+                } else if (fk[s] == 1) {
+                    const int r = HX + fa[s], c = fc[s];
 #pragma unroll
                     for (int l = 1; l <= R; ++l) {
-                        bf = fmaf(P.mj[l], cb[f + l + R - 1] + cb[f - l + R], bf);
-                        dp = fmaf(P.sx[l], cp[f + l + R - 1] - cp[f - l + R], dp);
+                        bf = fmaf(P.mj[l], sb[r][c + R - 1 + l] + sb[r][c + R - l], bf);
+                        dp = fmaf(P.sy[l], sp[r][c + R - 1 + l] - sp[r][c + R - l], dp);
                     }
-                    fx[f] = bf * dp;
-                }
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    float d = 0.0f;
-#pragma unroll
-                    for (int j = 1; j <= R; ++j) d = fmaf(P.sx[j], fx[i + j - 1 + R] - fx[i - j + R], d);
-                    dx[i] = d;
+                    sfy[fa[s]][fc[s]] = bf * dp;
                 }
             }
             __syncthreads();
 
-            // phase 3: assemble and update
+            // phase three: divergence and update
+            const int so = soff(z);
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const int row = wave * RPT + i;
-                float dzs = 0.0f, dys = 0.0f;
+                const int rr = wave * RPT + i;
+                float dzs = 0.0f, dxs = 0.0f, dys = 0.0f;
 #pragma unroll
                 for (int j = 1; j <= R; ++j) {
-                    dzs = fmaf(P.sz[j], fq[i][R + j - 1] - fq[i][R - j], dzs);
-                    dys = fmaf(P.sy[j], sfy[row][lane + j - 1 + R] - sfy[row][lane - j + R], dys);
+                    dzs = fmaf(P.sz[j], fq[i][(u + R + j - 1) % Q] - fq[i][(u + R - j) % Q], dzs);
+                    if constexpr (NDIM == 3) dxs = fmaf(P.sx[j], sfx[rr + R + j - 1][lane] - sfx[rr + R - j][lane], dxs);
+                    dys = fmaf(P.sy[j], sfy[rr][lane + R + j - 1] - sfy[rr][lane + R - j], dys);
                 }
-                const float lap = dzs + dx[i] + dys;
-                const float c = pq[i][0];
-                const float out = pa[i] * fmaf(pk[i], lap, 2.0f * c) - pb[i] * pp[i];
-                if (rin[i]) st_stream<NT>(out, nxt + int64_t(z) * sz + roff[i]);
+                const float lap = dzs + dxs + dys;
+                const float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, pq[i][u % Q], W.p[i]);
+                buf_st<NT>(out, rn, ro[i], so);
             }
         }
-#pragma unroll
-        for (int i = 0; i < RPT; ++i)
-#pragma unroll
-            for (int k = 0; k < 2 * R - 1; ++k) {
-                pq[i][k] = pq[i][k + 1];
-                bq[i][k] = bq[i][k + 1];
-                fq[i][k] = fq[i][k + 1];
-            }
+    }
     }
 }
 
