@@ -68,7 +68,7 @@ constexpr int kDefaultPF = 1;
 bool const_shape_ok(int tx, int nw)
 {
     return (tx == 16 && nw == 4) || (tx == 8 && nw == 4) || (tx == 32 && nw == 8) || (tx == 16 && nw == 8) ||
-           (tx == 8 && nw == 8);
+           (tx == 8 && nw == 8) || (tx == 24 && nw == 8);
 }
 
 bool wave_shape_ok(int tx, int nw)

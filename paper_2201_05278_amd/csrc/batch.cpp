@@ -342,7 +342,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     std::vector<Shape> shapes;
     const bool two = p->ndim == 3 && p->prob.scheme == SW_CONST && io->field2[0] && io->field2[1];
     if (p->ndim == 3 && p->prob.scheme == SW_CONST)
-        shapes = {{16, 4, 0, 1}, {8, 4, 0, 1}, {32, 8, 0, 1}, {16, 8, 0, 1}, {8, 8, 0, 1},
+        shapes = {{16, 4, 0, 1}, {8, 4, 0, 1}, {32, 8, 0, 1}, {16, 8, 0, 1}, {8, 8, 0, 1}, {24, 8, 0, 1},
                   {16, 4, 1, 1}, {32, 4, 1, 1}, {4, 1, 1, 1}, {8, 1, 1, 1}, {16, 2, 1, 1}};
     else if (p->ndim == 3)
         shapes = {{16, 8, 0, 1}, {8, 8, 0, 1}, {8, 4, 0, 1}, {16, 4, 0, 1}};
@@ -424,7 +424,7 @@ sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cach
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<std::pair<int, int>> shapes;
-    if (b->ndim == 3) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}, {8, 8}};
+    if (b->ndim == 3) shapes = {{16, 4}, {8, 4}, {32, 8}, {16, 8}, {8, 8}, {24, 8}};
     else shapes = {{1, 1}};
     hipEvent_t e0, e1;
     SW_HIP(hipEventCreate(&e0));

@@ -461,8 +461,16 @@ __global__ void __launch_bounds__(64 * NWB) k_const_wave(StencilParams P)
     const_wave_tile<R, NDIM, RW, NWB, MODE, NT>(P, xcd_remap(blockIdx.x, gridDim.x));
 }
 
+// Tall tiles of 8 waves (3 or more rows per thread) are held to 128 VGPRs so
+// that two blocks share a CU (up to radius 4; larger radii would spill).
+template <int R, int TX, int NW>
+constexpr int const_min_waves()
+{
+    return (R <= 4 && NW == 8 && TX / NW >= 3) ? 4 : 1;
+}
+
 template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
-__global__ void __launch_bounds__(64 * NW) k_const(StencilParams P)
+__global__ void __launch_bounds__(64 * NW, (const_min_waves<R, TX, NW>())) k_const(StencilParams P)
 {
     const_tile<R, NDIM, TX, NW, MODE, NT, PF>(P, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -497,7 +505,7 @@ __global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__
 }
 
 // Tile shapes (rows, waves) instantiated for 3D grids; 2D grids use (1, 1).
-#define SW_CONST_SHAPES(X) X(16, 4) X(8, 4) X(32, 8) X(16, 8) X(8, 8)
+#define SW_CONST_SHAPES(X) X(16, 4) X(8, 4) X(32, 8) X(16, 8) X(8, 8) X(24, 8)
 
 template <int R, int NDIM, int TX, int NW, int NT, int PF>
 hipError_t launch_const_shape(int mode, StencilParams &P, hipStream_t s)

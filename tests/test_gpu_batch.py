@@ -33,7 +33,8 @@ def test_tilings_are_bitwise_identical():
     tr_ref = ref.traces.clone()
     for tx, nw, zc, nt, pf, wt in [(8, 4, 0, 0, 1, 0), (32, 8, 13, 1, 2, 0), (16, 8, 100, 1, 1, 0),
                                    (16, 4, 9, 0, 2, 0), (8, 8, 20, 1, 2, 0), (16, 4, 17, 1, 0, 1),
-                                   (4, 1, 0, 0, 0, 1), (8, 1, 31, 1, 0, 1)]:
+                                   (4, 1, 0, 0, 0, 1), (8, 1, 31, 1, 0, 1), (24, 8, 11, 1, 1, 0),
+                                   (24, 8, 0, 0, 2, 0)]:
         print(f"case: tiling {tx}x{nw} zc={zc} nt={nt} pf={pf} wave={wt}", flush=True)
         prop.set_tiling(tx, nw, zc, nt, pf, wt)
         r = prop.forward(wav)
