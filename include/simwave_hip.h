@@ -143,7 +143,9 @@ typedef struct sw_plan sw_plan;
 /* Validate the problem and build a plan (host tables: coefficients, damping
  * table).  Checks dt against the stability limit is left to the model
  * prepare call, which knows c_max.  *out receives a plan owned by the caller
- * and released with sw_plan_destroy. */
+ * and released with sw_plan_destroy.  SW_ERR_UNSUPPORTED if a padded z plane
+ * times (4R + 2) reaches 2^31 bytes (the kernels address a window of planes
+ * with 32-bit offsets), e.g. planes beyond about 3800^2 nodes at SO16. */
 sw_status sw_plan_create(const sw_problem *prob, sw_plan **out);
 sw_status sw_plan_destroy(sw_plan *plan);
 /* Fill *out with the buffer sizes of the plan (after geometry is set the

@@ -350,9 +350,12 @@ sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
         p->prob.nbl[2][0] = p->prob.nbl[2][1] = 0;
     }
     build_layout(p);
-    if (int64_t(p->pad[1]) * p->pad[2] >= (int64_t(1) << 31)) {
+    // stencil launches address a window of at most (4R + 2) z planes with
+    // 32-bit byte offsets
+    if (int64_t(p->pad[1]) * p->pad[2] * 4 * (4 * p->r + 2) >= (int64_t(1) << 31)) {
         delete p;
-        return fail(SW_ERR_UNSUPPORTED, "a z plane of the padded grid exceeds 2^31 elements");
+        return fail(SW_ERR_UNSUPPORTED, "a z plane of the padded grid is too large for 32-bit window offsets "
+                                        "(plane bytes x (4R + 2) must stay below 2^31)");
     }
     *out = p;
     return SW_OK;

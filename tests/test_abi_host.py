@@ -110,6 +110,9 @@ def test_invalid_problems_refused():
     _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 20), (1.0, 1.0), 18, 1e-3, 5)
     _expect("SW_ERR_ARG", Propagator, (20, 20), (1.0, -1.0), 4, 1e-3, 5)
     _expect("SW_ERR_ARG", Propagator, (20, 20), (1.0, 1.0), 4, -1e-3, 5)
+    # a padded z plane too large for the 32-bit window offsets (9000^2 x 4 B x 18 planes)
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (4, 9000, 9000), (1.0,) * 3, 8, 1e-4, 5, nbl=0)
+    Propagator((4, 2000, 2000), (1.0,) * 3, 8, 1e-4, 5, nbl=0)
 
 
 def test_mirror_ghosts_refused():
