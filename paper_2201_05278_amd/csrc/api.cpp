@@ -114,10 +114,10 @@ Tiling choose_tiling(const sw_plan *p)
         t.tx = 1;
         t.nw = 1;
     } else if (p->prob.scheme != SW_CONST) {
-        // variable-density kernels: 8x8 staggered, 16x8 centred (tiling sweep, 592^3 SO8)
-        const int dtx = p->prob.scheme == SW_VD_STAGGERED ? 8 : 16;
-        t.tx = p->tile_tx ? p->tile_tx : dtx;
-        t.nw = p->tile_tx ? p->tile_nw : 8;
+        // variable-density kernels: 8x4 staggered, 16x8 centred (tiling sweep, 592^3 SO8)
+        const bool stag = p->prob.scheme == SW_VD_STAGGERED;
+        t.tx = p->tile_tx ? p->tile_tx : (stag ? 8 : 16);
+        t.nw = p->tile_tx ? p->tile_nw : (stag ? 4 : 8);
     } else if (p->tile_tx) {
         t.tx = p->tile_tx;
         t.nw = p->tile_nw;
@@ -147,6 +147,7 @@ void fill_params(const sw_plan *p, void *ws, StencilParams &P)
     P.g = make_geom(p);
     P.K = at<float>(ws, p->ws.model_k);
     P.aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
+    for (int a = 0; a < 3; ++a) P.face[a] = p->ws.face[a] ? at<float>(ws, p->ws.face[a]) : nullptr;
     P.damp = at<float2>(ws, p->ws.damp);
     P.ndamp = p->damp_n;
     double c0 = 0.0;
@@ -524,6 +525,13 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
     float *K = at<float>(ws, p->ws.model_k);
     float *aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
     SW_HIP(launch_model_prep(g, p->hz, p->hx, p->pad[0], p->prob.scheme, p->prob.dt, vel, rho, K, aux, s));
+    if (p->prob.scheme == SW_VD_STAGGERED) {
+        StencilParams F;
+        fill_params(p, ws, F);
+        SW_HIP(launch_face_buoyancy(g, p->hz, p->hx, p->pad[0], p->r, F.mj, aux,
+                                    const_cast<float *>(F.face[0]), const_cast<float *>(F.face[1]),
+                                    const_cast<float *>(F.face[2]), s));
+    }
     SW_HIP(hipMemcpyAsync(at<char>(ws, p->ws.damp), p->damp.data(), p->damp.size() * sizeof(float),
                           hipMemcpyHostToDevice, s));
     st = upload_points(p, p->src, p->ws.src, ws, s);

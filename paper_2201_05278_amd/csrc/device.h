@@ -40,6 +40,7 @@ struct StencilParams {
     const float *cur;       // p^n
     const float *K;         // multiplier of (L p): dt^2 c^2, or dt^2 rho c^2
     const float *aux;       // b = 1/rho (staggered) or rho (centred); unused otherwise
+    const float *face[3];   // staggered: face buoyancy b_{k+1/2} along z, x, y (stored at node k)
     const float2 *damp;     // (A, B) by squared layer distance
     int ndamp;              // entries of damp
     float *store;           // MODE_STORE: K (L p) written; MODE_IMAGE: read
@@ -121,6 +122,10 @@ hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int scheme,
                              double dt, const float *vel, const float *rho, float *K, float *aux,
                              hipStream_t s);
+// Staggered scheme: face buoyancies b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1})
+// along each axis (b at the nearest grid node), at every padded position.
+hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, int r, const float *mj,
+                                const float *b, float *fz, float *fx, float *fy, hipStream_t s);
 hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel,
                              double dt, double inv_dv, hipStream_t s);
 hipError_t launch_inject(const PointTableDev &t, float *field, float *store, const float *amp,

@@ -61,6 +61,44 @@ __global__ void k_model_prep(Geom g, int hz, int hx, int pz, int scheme, float d
     }
 }
 
+// Face buoyancies of the staggered operator at every padded position
+// (z, x, y): b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1}) along each axis, with
+// b read at the nearest node of the extended grid.  The sum runs j = 1..R with
+// fused multiply-adds in that order.
+struct FaceCoef {
+    float m[9];
+};
+
+__global__ void k_face_buoyancy(Geom g, int hz, int hx, int pz, int r, FaceCoef c,
+                                const float *__restrict__ b, float *__restrict__ fz,
+                                float *__restrict__ fx, float *__restrict__ fy)
+{
+    const int64_t total = int64_t(pz) * g.px * g.py;
+    auto at = [&](int z, int x, int y) -> float {
+        z = min(max(z, 0), g.Z - 1);
+        x = min(max(x, 0), g.X - 1);
+        y = min(max(y, 0), g.Y - 1);
+        return b[g.origin + (int64_t(z) * g.px + x) * g.py + y];
+    };
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int yy = int(i % g.py);
+        const int64_t t = i / g.py;
+        const int xx = int(t % g.px);
+        const int zz = int(t / g.px);
+        const int z = zz - hz, x = xx - hx, y = yy - 64;
+        float bz = 0.0f, bx = 0.0f, by = 0.0f;
+        for (int l = 1; l <= r; ++l) {
+            bz = fmaf(c.m[l], at(z + l, x, y) + at(z - l + 1, x, y), bz);
+            if (fx) bx = fmaf(c.m[l], at(z, x + l, y) + at(z, x - l + 1, y), bx);
+            by = fmaf(c.m[l], at(z, x, y + l) + at(z, x, y - l + 1), by);
+        }
+        fz[i] = bz;
+        if (fx) fx[i] = bx;
+        fy[i] = by;
+    }
+}
+
 // Per entry: A(node) dt^2 c(node)^2 w s (injection), dt^2 c^2 w s (the source
 // part of the stored M (L u + Q s) levels) and w s (recording), with s = 1/dV
 // for sources and 1 for receivers.
@@ -278,6 +316,17 @@ hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int 
     const int64_t total = int64_t(pz) * g.px * g.py;
     hipLaunchKernelGGL(k_model_prep, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, halo_z,
                        halo_x, pz, scheme, float(dt * dt), vel, rho, K, aux);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, int r, const float *mj,
+                                const float *b, float *fz, float *fx, float *fy, hipStream_t s)
+{
+    FaceCoef c{};
+    for (int l = 1; l <= r; ++l) c.m[l] = mj[l];
+    const int64_t total = int64_t(pz) * g.px * g.py;
+    hipLaunchKernelGGL(k_face_buoyancy, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, halo_z, halo_x, pz,
+                       r, c, b, fz, fx, fy);
     return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ struct PointSet {
 struct WorkspaceMap {
     size_t model_k = 0;      // float[field_elems]: K (dt^2 c^2, or dt^2 rho c^2)
     size_t model_aux = 0;    // float[field_elems]: b = 1/rho or rho (variable density)
+    size_t face[3] = {0, 0, 0};   // staggered: float[field_elems] face buoyancy b_{k+1/2} along z, x, y
     size_t damp = 0;         // float2[damp_n]: (A, B) by squared layer distance
     struct Pts {
         size_t ptr = 0, node = 0, pid = 0, d2 = 0, phys = 0, weight = 0;   // by point

@@ -52,7 +52,6 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     constexpr int Q = 2 * R;                      // queue length (even: slots alternate)
     constexpr int kOut = 0x7ffffe00;
     __shared__ float sp[LX + 1][LY];              // last row: sink for idle items
-    __shared__ float sb[LX + 1][LY];
     __shared__ float sfx[FX + 1][64];
     __shared__ float sfy[TX + 1][FY];
 
@@ -71,7 +70,6 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const int ze = min(zb + P.zc, g.Z);
     const int64_t sz = int64_t(g.px) * g.py;
     const bool yin = y < g.Y;
-    const int yc = clampi(y, 0, g.Y - 1);
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
     // z window: planes zw .. zt - 1 (the queue reaches 2R - 1 planes ahead)
     const int zw = max(zb - 2 * R + 1, 0);
@@ -80,41 +78,52 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const uint32_t wbytes = uint32_t(zt - zw) * uint32_t(pb);
     const int64_t w0 = g.base + int64_t(zw) * sz;
     const auto rc = buf_res(P.cur + w0, wbytes);
-    const auto rbm = buf_res(P.aux + w0, wbytes);
     const auto rn = buf_res(P.nxt + w0, wbytes);
+    // face buoyancies: planes fw .. fw + zc + 2R - 1 (faces zb - R .. ze + R - 2 along
+    // z; the padded halo of 2R planes holds those off the grid)
+    const int fw = zb - R;
+    const uint32_t fbytes = uint32_t(ze - zb + 2 * R) * uint32_t(pb);
+    const int64_t f0 = g.base + int64_t(fw) * sz;
+    const auto rfz = buf_res(P.face[0] + f0, fbytes);
+    const auto rfx = buf_res((NDIM == 3 ? P.face[1] : P.face[0]) + f0, fbytes);
+    const auto rfy = buf_res(P.face[2] + f0, fbytes);
+    auto fsoff = [&](int z) -> int { return (z - fw) * pb; };
     const auto rk = buf_res(P.K + w0, wbytes);
     const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
     auto soff = [&](int z) -> int { return (clampi(z, zw, zt - 1) - zw) * pb; };
     auto keep = [](float v, unsigned m) -> float {
         return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m);
     };
-    // byte offsets in a plane: wavefield (zero off the grid) and model (nearest grid node)
+    // byte offsets in a plane: wavefield (zero off the grid); faces (inside the
+    // padded plane for faces -R .. n + R - 2 of every axis, out of range otherwise:
+    // those only feed nodes off the grid)
     auto off = [&](int x, int yy) -> int {
         return (x >= 0 && x < g.X && yy >= 0 && yy < g.Y) ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
-    auto moff = [&](int x, int yy) -> int { return (g.xy0 + clampi(x, 0, g.X - 1) * g.py + clampi(yy, 0, g.Y - 1)) * 4; };
+    auto foff = [&](int x, int yy) -> int {
+        const bool ok = (NDIM == 2 || (x >= -R && x <= g.X + R - 2)) && yy >= -R && yy <= g.Y + R - 2;
+        return ok ? (g.xy0 + x * g.py + yy) * 4 : kOut;
+    };
 
-    int ro[RPT], rm[RPT], ex2[RPT];
+    int ro[RPT], ex2[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         const bool in = yin && x < g.X;
         ro[i] = off(x, y);
-        rm[i] = moff(x, y);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = in ? ex * ex + ey * ey : 0;
     }
-    int hxo[HXN > 0 ? HXN : 1], hxm[HXN > 0 ? HXN : 1], hxrow[HXN > 0 ? HXN : 1];
+    int hxo[HXN > 0 ? HXN : 1], hxrow[HXN > 0 ? HXN : 1];
 #pragma unroll
     for (int s = 0; s < HXN; ++s) {
         const int hr = wave + s * NW;
         const bool ok = hr < 2 * HX;
         const int x = (hr < HX) ? x0 - HX + hr : x0 + TX + hr - HX;
         hxo[s] = ok ? off(x, y) : kOut;
-        hxm[s] = moff(x, y);
         hxrow[s] = !ok ? LX : (hr < HX) ? hr : TX + hr;
     }
-    int hyo[YHN], hym[YHN], hyrow[YHN], hycol[YHN];
+    int hyo[YHN], hyrow[YHN], hycol[YHN];
 #pragma unroll
     for (int s = 0; s < YHN; ++s) {
         const int e = threadIdx.x + s * NTH;
@@ -123,31 +132,35 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const int yy = (c < H) ? y0 - H + c : y0 + 64 + c - H;
         const int x = x0 + row;
         hyo[s] = ok ? off(x, yy) : kOut;
-        hym[s] = moff(x, yy);
         hyrow[s] = ok ? HX + row : LX;
         hycol[s] = (c < H) ? c : 64 + c;
     }
-    // face items of phase two: kind 0 x face (row t, lane column), 1 y face
-    // (tile row r, face column c), 2 idle (written to the sink rows)
-    int fk[NIT], fa[NIT], fc[NIT];
+    // face items of phase two: kind 0 x face (row t, lane column), kind 1 y face
+    // (tile row r, face column c); idle items are y faces of the sink row with
+    // an out-of-range face offset.  The kind is uniform over a wavefront.
+    int fk[NIT], fa[NIT], fc[NIT], fo[NIT];
 #pragma unroll
     for (int s = 0; s < NIT; ++s) {
         const int e = threadIdx.x + s * NTH;
         if (e < FXR * 64) {
             fk[s] = 0; fa[s] = e / 64; fc[s] = e % 64;
+            fo[s] = foff(x0 - R + fa[s], y0 + fc[s]);
         } else if (e < (FXR + TX) * 64) {
             fk[s] = 1; fa[s] = e / 64 - FXR; fc[s] = e % 64;
+            fo[s] = foff(x0 + fa[s], y0 - R + fc[s]);
         } else if (e < NI) {
             const int t = e - (FXR + TX) * 64;
             fk[s] = 1; fa[s] = t / (2 * R - 1); fc[s] = 64 + t % (2 * R - 1);
+            fo[s] = foff(x0 + fa[s], y0 - R + fc[s]);
         } else {
-            fk[s] = 2; fa[s] = TX; fc[s] = 0;
+            fk[s] = 1; fa[s] = TX; fc[s] = 0; fo[s] = kOut;
         }
+        fk[s] = __builtin_amdgcn_readfirstlane(fk[s]);
     }
 
     // queues, rotating with the unrolled step u: pq[(u + k) % Q] = p(z + k),
-    // bq[(u + k) % Q] = b(z + k), fq[(u + k) % Q] = z flux at face (z - R + k) + 1/2
-    float pq[RPT][Q], bq[RPT][Q], fq[RPT][Q];
+    // fq[(u + k) % Q] = z flux at face (z - R + k) + 1/2
+    float pq[RPT][Q], fq[RPT][Q];
     const int zs = zb - 2 * R + 1;
 #pragma unroll
     for (int k = 0; k < 2 * R - 1; ++k) {
@@ -155,10 +168,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const unsigned m = (z >= 0 && z < g.Z) ? ~0u : 0u;
         const int so = soff(z);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            pq[i][k] = keep(buf_ld<0>(rc, ro[i], so), m);
-            bq[i][k] = buf_ld<0>(rbm, rm[i], so);
-        }
+        for (int i = 0; i < RPT; ++i) pq[i][k] = keep(buf_ld<0>(rc, ro[i], so), m);
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
@@ -166,22 +176,27 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         for (int k = 0; k < 2 * R; ++k) fq[i][k] = 0.0f;
 
     struct Slot {
-        float fp[RPT], fb[RPT], p[RPT], k[RPT];
+        float fp[RPT], fz[RPT], p[RPT], k[RPT];
         float2 ab[RPT];
-        float hxp[HXN > 0 ? HXN : 1], hxb[HXN > 0 ? HXN : 1], hyp[YHN], hyb[YHN];
+        float hxp[HXN > 0 ? HXN : 1], hyp[YHN], ff[NIT];
     };
-    // loads of plane z: the queue input at z + 2R - 1, and for z >= zb the
-    // plane's own p^{n-1}, K, (A, B) and the halos of p and b
+    // loads of plane z: the queue input at z + 2R - 1 and the z-face buoyancy at
+    // z + R - 1, and for z >= zb the plane's own p^{n-1}, K, (A, B), the halos
+    // of p and the x / y face buoyancies of the thread's face items
     auto load = [&](int z, Slot &L) {
         const int zf = z + 2 * R - 1;
         const unsigned mf = zf < g.Z ? ~0u : 0u;
-        const int sf = soff(zf);
+        const int sf = soff(zf), sfz = fsoff(z + R - 1);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             L.fp[i] = keep(buf_ld<0>(rc, ro[i], sf), mf);
-            L.fb[i] = buf_ld<0>(rbm, rm[i], sf);
+            L.fz[i] = buf_ld<NT>(rfz, ro[i], sfz);
         }
         if (z < zb) return;
+        const int sff = fsoff(z);
+#pragma unroll
+        for (int s = 0; s < NIT; ++s)
+            L.ff[s] = (NDIM == 3 && fk[s] == 0) ? buf_ld<0>(rfx, fo[s], sff) : buf_ld<0>(rfy, fo[s], sff);
         const int so = soff(z);
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
 #pragma unroll
@@ -191,15 +206,9 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
             L.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
         }
 #pragma unroll
-        for (int s = 0; s < HXN; ++s) {
-            L.hxp[s] = buf_ld<0>(rc, hxo[s], so);
-            L.hxb[s] = buf_ld<0>(rbm, hxm[s], so);
-        }
+        for (int s = 0; s < HXN; ++s) L.hxp[s] = buf_ld<0>(rc, hxo[s], so);
 #pragma unroll
-        for (int s = 0; s < YHN; ++s) {
-            L.hyp[s] = buf_ld<0>(rc, hyo[s], so);
-            L.hyb[s] = buf_ld<0>(rbm, hym[s], so);
-        }
+        for (int s = 0; s < YHN; ++s) L.hyp[s] = buf_ld<0>(rc, hyo[s], so);
     };
 
     Slot S[2];
@@ -212,61 +221,41 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         Slot &W = S[u % 2];
         if (z + 1 < ze) load(z + 1, S[(u + 1) % 2]);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            pq[i][(u + 2 * R - 1) % Q] = W.fp[i];
-            bq[i][(u + 2 * R - 1) % Q] = W.fb[i];
-        }
+        for (int i = 0; i < RPT; ++i) pq[i][(u + 2 * R - 1) % Q] = W.fp[i];
         // z flux at face (z + R - 1) + 1/2
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            float bf = 0.0f, dp = 0.0f;
+            float dp = 0.0f;
 #pragma unroll
-            for (int l = 1; l <= R; ++l) {
-                bf = fmaf(P.mj[l], bq[i][(u + R - 1 + l) % Q] + bq[i][(u + R - l) % Q], bf);
+            for (int l = 1; l <= R; ++l)
                 dp = fmaf(P.sz[l], pq[i][(u + R - 1 + l) % Q] - pq[i][(u + R - l) % Q], dp);
-            }
-            fq[i][(u + 2 * R - 1) % Q] = bf * dp;
+            fq[i][(u + 2 * R - 1) % Q] = W.fz[i] * dp;
         }
 
         if (z >= zb) {
-            // phase one: stage p and b of plane z with an H-node halo
+            // phase one: stage p of plane z with an H-node halo
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                sp[HX + wave * RPT + i][H + lane] = pq[i][u % Q];
-                sb[HX + wave * RPT + i][H + lane] = bq[i][u % Q];
-            }
+            for (int i = 0; i < RPT; ++i) sp[HX + wave * RPT + i][H + lane] = pq[i][u % Q];
 #pragma unroll
-            for (int s = 0; s < HXN; ++s) {
-                sp[hxrow[s]][H + lane] = W.hxp[s];
-                sb[hxrow[s]][H + lane] = W.hxb[s];
-            }
+            for (int s = 0; s < HXN; ++s) sp[hxrow[s]][H + lane] = W.hxp[s];
 #pragma unroll
-            for (int s = 0; s < YHN; ++s) {
-                sp[hyrow[s]][hycol[s]] = W.hyp[s];
-                sb[hyrow[s]][hycol[s]] = W.hyb[s];
-            }
+            for (int s = 0; s < YHN; ++s) sp[hyrow[s]][hycol[s]] = W.hyp[s];
             __syncthreads();
 
             // phase two: every x and y face flux of the tile, once
 #pragma unroll
             for (int s = 0; s < NIT; ++s) {
-                float bf = 0.0f, dp = 0.0f;
+                float dp = 0.0f;
                 if (NDIM == 3 && fk[s] == 0) {
                     const int t = fa[s], c = H + fc[s];
 #pragma unroll
-                    for (int l = 1; l <= R; ++l) {
-                        bf = fmaf(P.mj[l], sb[t + R - 1 + l][c] + sb[t + R - l][c], bf);
-                        dp = fmaf(P.sx[l], sp[t + R - 1 + l][c] - sp[t + R - l][c], dp);
-                    }
-                    sfx[t][fc[s]] = bf * dp;
-                } else if (fk[s] == 1) {
+                    for (int l = 1; l <= R; ++l) dp = fmaf(P.sx[l], sp[t + R - 1 + l][c] - sp[t + R - l][c], dp);
+                    sfx[t][fc[s]] = W.ff[s] * dp;
+                } else {
                     const int r = HX + fa[s], c = fc[s];
 #pragma unroll
-                    for (int l = 1; l <= R; ++l) {
-                        bf = fmaf(P.mj[l], sb[r][c + R - 1 + l] + sb[r][c + R - l], bf);
-                        dp = fmaf(P.sy[l], sp[r][c + R - 1 + l] - sp[r][c + R - l], dp);
-                    }
-                    sfy[fa[s]][fc[s]] = bf * dp;
+                    for (int l = 1; l <= R; ++l) dp = fmaf(P.sy[l], sp[r][c + R - 1 + l] - sp[r][c + R - l], dp);
+                    sfy[fa[s]][fc[s]] = W.ff[s] * dp;
                 }
             }
             __syncthreads();

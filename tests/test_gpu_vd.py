@@ -2,8 +2,11 @@
 centred) against the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
+import torch
 
+import oracle
 import workloads
+from paper_2201_05278_amd import Propagator
 from tests.test_gpu_forward import run_pair, rel, field_np, TOL
 
 pytestmark = pytest.mark.gpu
@@ -64,3 +67,32 @@ def test_vd_density_scale_invariance():
     _, r2, _, _ = run_pair(n, h, 8, 5, 80, vel, src, rec, scheme="vd_staggered",
                            rho=(rho * 1000.0).astype(np.float32))
     assert rel(r2.traces.cpu().numpy(), r1.traces.cpu().numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("scheme", ["vd_staggered", "vd_centred"])
+def test_vd_tilings_are_bitwise_identical(scheme):
+    # the per-node (and per-face) arithmetic does not depend on the tile shape,
+    # chunk length or cache policy
+    n = (30, 37, 70)
+    rng = np.random.default_rng(41)
+    vel = workloads.layered(n, [1500.0, 2500.0, 3500.0], rng, 40.0)
+    rho = workloads.gardner(vel)
+    h = (10.0,) * 3
+    dt = workloads.CFL_FRACTION * oracle.coeffs.critical_dt(h, 8, float(vel.max()))
+    prop = Propagator(n, h, 8, dt, 50, scheme=scheme, nbl=5)
+    prop.set_sources([[150.0, 183.0, 344.0]])
+    prop.set_receivers([[0.0, 10.0 * k + 3.0, 8.0 * k] for k in range(30)])
+    prop.prepare(torch.from_numpy(vel).cuda(), torch.from_numpy(rho).cuda())
+    wav = torch.from_numpy(oracle.ricker(15.0, dt, 50)[:, None].astype(np.float32)).cuda()
+    ref = prop.forward(wav)
+    torch.cuda.synchronize()
+    u_ref = prop.grid_view(ref.fields[ref.current]).clone()
+    tr_ref = ref.traces.clone()
+    for tx, nw, zc, nt in [(8, 8, 0, 1), (16, 8, 7, 0), (8, 4, 13, 1), (16, 4, 25, 0), (8, 4, 1, 0)]:
+        print(f"case: {scheme} tiling {tx}x{nw} zc={zc} nt={nt}", flush=True)
+        prop.set_tiling(tx, nw, zc, nt)
+        r = prop.forward(wav)
+        torch.cuda.synchronize()
+        assert torch.equal(r.traces, tr_ref)
+        assert torch.equal(prop.grid_view(r.fields[r.current]), u_ref)
+    prop.set_tiling()
