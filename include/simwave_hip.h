@@ -65,7 +65,8 @@ extern "C" {
 typedef enum sw_status {
     SW_OK = 0,
     SW_ERR_ARG = 1,          /* invalid argument (null pointer, bad size, ...) */
-    SW_ERR_UNSUPPORTED = 2,  /* valid but not provided (odd or >16 order, mirror ghosts, ...) */
+    SW_ERR_UNSUPPORTED = 2,  /* valid but not provided (odd or >16 order, mirror ghosts in
+                                the adjoint, ...) */
     SW_ERR_DOMAIN = 3,       /* a point lies outside the physical grid or its footprint
                                 leaves the extended grid */
     SW_ERR_CFL = 4,          /* dt above the stability limit */
@@ -88,7 +89,14 @@ typedef struct sw_problem {
     int32_t space_order;    /* even, 2..16 */
     int32_t scheme;         /* SW_CONST, SW_VD_STAGGERED or SW_VD_CENTRED */
     int32_t nbl[3][2];      /* absorbing layer cells (low side, high side) per axis */
-    int32_t bc[3][2];       /* ghost condition per side; this library: SW_BC_NONE */
+    int32_t bc[3][2];       /* ghost condition per side at the edge of the extended grid
+                               (paper, "Boundary conditions and domain truncation"):
+                               SW_BC_NONE (ghosts read zero), SW_BC_DIRICHLET (odd
+                               mirror about the boundary node, which is held at zero)
+                               or SW_BC_NEUMANN (even mirror).  Mirror sides need at
+                               least R + 1 nodes (2R staggered) along their axis, are
+                               served by the forward with single sweeps of block
+                               tiles, and are refused by the adjoint and batches. */
     double  damp_alpha;     /* alpha of eta = alpha d^p (paper default 0.001) */
     double  damp_power;     /* p (paper default 3) */
     double  dt;             /* time step, seconds */

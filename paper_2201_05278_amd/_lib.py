@@ -21,6 +21,7 @@ SW_SRC, SW_REC = 0, 1
 SW_INTERP_HICKS, SW_INTERP_LINEAR = 0, 1
 SCHEMES = {"const": SW_CONST, "vd_staggered": SW_VD_STAGGERED, "vd_centred": SW_VD_CENTRED}
 INTERPS = {"hicks": SW_INTERP_HICKS, "linear": SW_INTERP_LINEAR}
+BCS = {"none": 0, "dirichlet": 1, "neumann": 2}
 
 STATUS = {0: "SW_OK", 1: "SW_ERR_ARG", 2: "SW_ERR_UNSUPPORTED", 3: "SW_ERR_DOMAIN",
           4: "SW_ERR_CFL", 5: "SW_ERR_STATE", 6: "SW_ERR_WORKSPACE", 7: "SW_ERR_HIP",

@@ -121,7 +121,11 @@ Tiling choose_tiling(const sw_plan *p)
     } else if (p->tile_tx) {
         t.tx = p->tile_tx;
         t.nw = p->tile_nw;
-        t.wt = p->tile_wt;
+        t.wt = p->mirror ? 0 : p->tile_wt;
+        if (p->tile_wt && p->mirror) {   // wave tiles read no ghosts: the default block tile instead
+            t.tx = 8;
+            t.nw = 4;
+        }
         t.ts = p->tile_ts == 2 ? 2 : 1;
     } else if (p->tile_ts == 2) {
         t.tx = 8;
@@ -150,6 +154,9 @@ void fill_params(const sw_plan *p, void *ws, StencilParams &P)
     for (int a = 0; a < 3; ++a) P.face[a] = p->ws.face[a] ? at<float>(ws, p->ws.face[a]) : nullptr;
     P.damp = at<float2>(ws, p->ws.damp);
     P.ndamp = p->damp_n;
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s) P.bcm[a][s] = p->bcm[a][s];
+    P.gh = p->ghost;
     double c0 = 0.0;
     const double h2z = p->hh[0] * p->hh[0], h2x = p->hh[1] * p->hh[1], h2y = p->hh[2] * p->hh[2];
     c0 += p->v2[0] / h2z + p->v2[0] / h2y;
@@ -191,7 +198,7 @@ hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s)
 
 bool two_step_ready(const sw_plan *p, const sw_fwd_io *io)
 {
-    return p->ndim == 3 && p->prob.scheme == SW_CONST && io->field2[0] && io->field2[1] &&
+    return p->ndim == 3 && p->prob.scheme == SW_CONST && !p->mirror && io->field2[0] && io->field2[1] &&
            choose_tiling(p).ts == 2;
 }
 
@@ -249,9 +256,8 @@ sw_status check_problem(const sw_problem *q)
             return fail(SW_ERR_ARG, "grid spacing must be positive");
         for (int s = 0; s < 2; ++s) {
             if (q->nbl[i][s] < 0) return fail(SW_ERR_ARG, "layer widths must be >= 0");
-            if (q->bc[i][s] != SW_BC_NONE)
-                return fail(SW_ERR_UNSUPPORTED,
-                            "mirror ghost conditions are not provided by this library");
+            if (q->bc[i][s] != SW_BC_NONE && q->bc[i][s] != SW_BC_DIRICHLET && q->bc[i][s] != SW_BC_NEUMANN)
+                return fail(SW_ERR_ARG, "unknown ghost condition");
         }
         if (int64_t(q->n[i]) + q->nbl[i][0] + q->nbl[i][1] > (1 << 20))
             return fail(SW_ERR_ARG, "grid extent too large");
@@ -351,6 +357,22 @@ sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
         p->prob.nbl[2][0] = p->prob.nbl[2][1] = 0;
     }
     build_layout(p);
+    // ghost conditions on the internal axes (z, x, y); a 2D grid is (z, 1, x)
+    p->ghost = p->prob.scheme == SW_VD_STAGGERED ? 2 * p->r - 1 : p->r;
+    for (int s = 0; s < 2; ++s) {
+        p->bcm[0][s] = p->prob.bc[0][s];
+        p->bcm[1][s] = p->ndim == 3 ? p->prob.bc[1][s] : SW_BC_NONE;
+        p->bcm[2][s] = p->ndim == 3 ? p->prob.bc[2][s] : p->prob.bc[1][s];
+    }
+    for (int a = 0; a < 3; ++a)
+        if (p->bcm[a][0] || p->bcm[a][1]) {
+            p->mirror = true;
+            if (p->dims[a] < p->ghost + 1) {
+                delete p;
+                return fail(SW_ERR_UNSUPPORTED, "a mirror ghost condition needs at least " +
+                                                    std::to_string(p->ghost + 1) + " nodes along its axis");
+            }
+        }
     // stencil launches address a window of at most (4R + 2) z planes with
     // 32-bit byte offsets
     if (int64_t(p->pad[1]) * p->pad[2] * 4 * (4 * p->r + 2) >= (int64_t(1) << 31)) {
@@ -381,6 +403,8 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
     }
     if (d.pf < 0 || d.pf > 2) return fail(SW_ERR_ARG, "pf must be 0, 1 or 2");
     if (d.wt && p->prob.scheme != SW_CONST) return fail(SW_ERR_UNSUPPORTED, "wave tiles cover constant density");
+    if ((d.wt || d.ts == 2) && p->mirror)
+        return fail(SW_ERR_UNSUPPORTED, "wave tiles and two-step sweeps read no mirror ghosts");
     if (d.tx || d.nw) {
         if (p->ndim != 3) return fail(SW_ERR_UNSUPPORTED, "2D grids have a fixed tile shape");
         const bool ok = p->prob.scheme != SW_CONST ? vd_shape_ok(d.tx, d.nw)
@@ -611,6 +635,7 @@ static sw_status enqueue_forward(sw_plan *p, const sw_fwd_io *io, hipStream_t s)
             continue;
         }
         SW_HIP(checkpoint(n, cur, nxt));
+        if (p->mirror) SW_HIP(launch_ghost_fill(g, p->bcm, p->ghost, cur, s));
         P.cur = cur;
         P.nxt = nxt;
         if (!ev.empty()) SW_HIP(hipEventRecord(ev[2 * k], s));
@@ -705,10 +730,12 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
 {
     set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
-    sw_status st = check_prepared(p, io->workspace);
-    if (st != SW_OK) return st;
     if (p->prob.scheme != SW_CONST)
         return fail(SW_ERR_UNSUPPORTED, "the adjoint covers the constant-density scheme");
+    if (p->mirror)
+        return fail(SW_ERR_UNSUPPORTED, "the adjoint covers zero ghosts (no Dirichlet / Neumann sides)");
+    sw_status st = check_prepared(p, io->workspace);
+    if (st != SW_OK) return st;
     if (!io->residual || !io->ckpt || io->ckpt_every <= 0 || !io->field[0] || !io->field[1] ||
         !io->adj[0] || !io->adj[1] || !io->segment || !io->grad_m || !io->grad_vel || !io->vel)
         return fail(SW_ERR_ARG, "missing buffer");

@@ -229,6 +229,7 @@ sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out)
         if (!p) return fail(SW_ERR_ARG, "plan is NULL");
         if (p->prob.scheme != SW_CONST)
             return fail(SW_ERR_UNSUPPORTED, "batches cover the constant-density scheme");
+        if (p->mirror) return fail(SW_ERR_UNSUPPORTED, "batches cover zero ghosts (no Dirichlet / Neumann sides)");
         if (p->ndim != p0->ndim || p->r != p0->r || p->prob.nsteps != p0->prob.nsteps)
             return fail(SW_ERR_ARG, "all shots need the same ndim, space order and step count");
     }

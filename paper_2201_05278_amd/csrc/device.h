@@ -51,7 +51,23 @@ struct StencilParams {
     float sz[9], sx[9], sy[9];     // staggered s_j / h, or centred c_j / h (first derivative)
     float mj[9];            // midpoint interpolation weights
     int ntx, nty, nzc, zc;  // tiling: tiles along x, y; z chunks and chunk length
+    int bcm[3][2];          // ghost condition per internal axis (z, x, y) and side: 0 zero, 1 Dirichlet, 2 Neumann
+    int gh;                 // ghost layers held in the stored halo (mirror sides)
 };
+
+// Whether the wavefield at coordinate v of an axis of extent n is read from
+// memory: grid nodes, and ghost nodes within the stored halo on a side with a
+// mirror condition (filled before the sweep); other positions read zero.
+__device__ inline bool axis_read(int v, int n, int lo, int hi, int h)
+{
+    return (v >= 0 && v < n) || (v < 0 && lo != 0 && v >= -h) || (v >= n && hi != 0 && v < n + h);
+}
+
+// Whether coordinate v lies on a side held at zero by a Dirichlet condition.
+__device__ inline bool axis_dirichlet(int v, int n, int lo, int hi)
+{
+    return (v == 0 && lo == 1) || (v == n - 1 && hi == 1);
+}
 
 // Tiling chosen by the host for one stencil launch.
 struct Tiling {
@@ -118,6 +134,10 @@ hipError_t launch_record_batch(const ShotPoints *shots, int nshots, int max_coun
                                int step, int parity, hipStream_t s);
 
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+// Mirror ghosts of a wavefield: for every side with a Dirichlet (odd) or
+// Neumann (even) condition, ghost layer k = 1..depth takes +-p at the node k
+// inside the boundary node, along z, then x, then y.
+hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, float *field, hipStream_t s);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int scheme,
                              double dt, const float *vel, const float *rho, float *K, float *aux,

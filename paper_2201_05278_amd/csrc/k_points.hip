@@ -61,6 +61,39 @@ __global__ void k_model_prep(Geom g, int hz, int hx, int pz, int scheme, float d
     }
 }
 
+// Mirror ghosts along one axis: thread i covers one (ghost layer, side, row of
+// the other two axes) item; ghost node at distance k outside the boundary node
+// takes sign * p at distance k inside it.
+__global__ void k_ghost_axis(Geom g, int axis, int lo, int hi, int depth, float *__restrict__ f)
+{
+    const int n[3] = {g.Z, g.X, g.Y};
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    const int64_t rows = int64_t(n[a1]) * n[a2];
+    const int64_t total = rows * depth * 2;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = i % rows;
+        const int k = 1 + int((i / rows) % depth);
+        const int side = int(i / (rows * depth));
+        const int bc = side ? hi : lo;
+        if (bc == 0) continue;
+        const int c[3] = {0, 0, 0};
+        int src[3] = {c[0], c[1], c[2]}, dst[3] = {c[0], c[1], c[2]};
+        src[a1] = dst[a1] = int(r / n[a2]);
+        src[a2] = dst[a2] = int(r % n[a2]);
+        if (side == 0) {
+            dst[axis] = -k;
+            src[axis] = k;
+        } else {
+            dst[axis] = n[axis] - 1 + k;
+            src[axis] = n[axis] - 1 - k;
+        }
+        if (src[axis] < 0 || src[axis] >= n[axis]) continue;   // extent below the ghost depth
+        const float v = f[elem(g, src[0], src[1], src[2])];
+        f[elem(g, dst[0], dst[1], dst[2])] = bc == 1 ? -v : v;
+    }
+}
+
 // Face buoyancies of the staggered operator at every padded position
 // (z, x, y): b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1}) along each axis, with
 // b read at the nearest node of the extended grid.  The sum runs j = 1..R with
@@ -317,6 +350,21 @@ hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int 
     hipLaunchKernelGGL(k_model_prep, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, halo_z,
                        halo_x, pz, scheme, float(dt * dt), vel, rho, K, aux);
     return hipGetLastError();
+}
+
+hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, float *field, hipStream_t s)
+{
+    const int n[3] = {g.Z, g.X, g.Y};
+    for (int axis = 0; axis < 3; ++axis) {
+        if (!bcm[axis][0] && !bcm[axis][1]) continue;
+        const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+        const int64_t total = int64_t(n[a1]) * n[a2] * depth * 2;
+        hipLaunchKernelGGL(k_ghost_axis, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, axis, bcm[axis][0],
+                           bcm[axis][1], depth, field);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, int r, const float *mj,

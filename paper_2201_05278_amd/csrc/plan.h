@@ -60,6 +60,9 @@ struct WorkspaceMap {
 
 struct sw_plan {
     sw_problem prob{};
+    int bcm[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // ghost condition per internal axis (z, x, y) and side
+    int ghost = 0;                  // mirror ghost layers a sweep reads (R, or 2R - 1 staggered)
+    bool mirror = false;            // any side with a Dirichlet or Neumann condition
     int ndim = 3;
     int r = 4;
     int halo = 4;

@@ -122,8 +122,10 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     const bool yin = y < g.Y;
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
     // z window of this chunk: planes zw .. zt - 1, plane z at byte offset (z - zw) * pb
-    const int zw = max(zb - R, 0);
-    const int zt = min(ze + R, g.Z);
+    // (planes off the grid lie in the stored halo: they hold mirror ghosts, or are
+    // masked to zero)
+    const int zw = zb - R;
+    const int zt = ze + R;
     const int pb = int(sz) * 4;
     const uint32_t wbytes = uint32_t(zt - zw) * uint32_t(pb);
     const int64_t w0 = g.base + int64_t(zw) * sz;
@@ -134,26 +136,39 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     __amdgpu_buffer_rsrc_t rs = rk, rg = rk;
     if constexpr (MODE != MODE_FWD) rs = buf_res(P.store + w0, wbytes);
     if constexpr (MODE == MODE_IMAGE) rg = buf_res(P.grad + w0, wbytes);
-    // byte offset of plane z in the window (planes below it clamp to its first plane)
-    auto soff = [&](int z) -> int { return max(z - zw, 0) * pb; };
+    // byte offset of plane z in the window
+    auto soff = [&](int z) -> int { return (z - zw) * pb; };
+    // planes read from memory: grid planes and mirror ghost planes
+    auto zmask = [&](int z) -> unsigned {
+        return axis_read(z, g.Z, P.bcm[0][0], P.bcm[0][1], P.gh) ? ~0u : 0u;
+    };
+    auto zdir = [&](int z) -> bool { return axis_dirichlet(z, g.Z, P.bcm[0][0], P.bcm[0][1]); };
     // keep a loaded value (mask ~0) or replace it by +0 (mask 0)
     auto keep = [](float v, unsigned m) -> float { return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m); };
-    // in-plane byte offsets: (xy0 + x py + y) * 4; nodes outside the grid get an
-    // offset past every window, so their loads read zero and their stores are dropped
+    // in-plane byte offsets: (xy0 + x py + y) * 4; nodes off the grid (other than
+    // mirror ghosts, for reads) get an offset past every window, so their loads
+    // read zero and their stores are dropped
     auto off = [&](int x, int yy) -> int { return (g.xy0 + x * g.py + yy) * 4; };
     constexpr int kOut = 0x7ffffe00;
+    auto rd_ok = [&](int x, int yy) -> bool {
+        return axis_read(x, g.X, P.bcm[1][0], P.bcm[1][1], P.gh) &&
+               axis_read(yy, g.Y, P.bcm[2][0], P.bcm[2][1], P.gh);
+    };
 
     // the tile lies inside the physical box along x and y: (A, B) = (1, 1) on
     // every plane whose z is outside the layer, no table reads there
     const bool inner_xy = x0 >= g.lo[1] && x0 + TX <= g.lo[1] + g.np[1] && y0 >= g.lo[2] &&
                           y0 + 64 <= g.lo[2] + g.np[2];
-    int ro[RPT], ex2[RPT];
-    bool rin[RPT];
+    int ro[RPT], rr[RPT], ex2[RPT];
+    bool rin[RPT], rdir[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         rin[i] = yin && x < g.X;
-        ro[i] = rin[i] ? off(x, y) : kOut;
+        ro[i] = rin[i] ? off(x, y) : kOut;              // stores and per-node arrays
+        rr[i] = rd_ok(x, y) ? off(x, y) : kOut;         // wavefield reads
+        rdir[i] = axis_dirichlet(x, g.X, P.bcm[1][0], P.bcm[1][1]) ||
+                  axis_dirichlet(y, g.Y, P.bcm[2][0], P.bcm[2][1]);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = rin[i] ? ex * ex + ey * ey : 0;      // keeps table reads in range
     }
@@ -164,7 +179,7 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         const int hr = wave + s * NW;
         hxok[s] = hr < 2 * R;
         const int x = (hr < R) ? x0 - R + hr : x0 + TX + hr - R;
-        hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
+        hxin[s] = hxok[s] && rd_ok(x, y);
         hxrow[s] = !hxok[s] ? LX : (hr < R) ? hr : TX + hr;
         hxo[s] = hxin[s] ? off(x, y) : kOut;
     }
@@ -177,7 +192,7 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         const int row = e / (2 * R), c = e % (2 * R);
         const int yy = (c < R) ? y0 - R + c : y0 + 64 + c - R;
         const int x = x0 + row;
-        hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
+        hyin[s] = hyok[s] && rd_ok(x, yy);
         hyrow[s] = hyok[s] ? HXR + row : LX;
         hycol[s] = (c < R) ? c : 64 + c;
         hyo[s] = hyin[s] ? off(x, yy) : kOut;
@@ -188,10 +203,10 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
         const int z = zb - R + k;
-        const unsigned zm = (z >= 0 && z < g.Z) ? ~0u : 0u;
-        const int so = soff(min(z, zt - 1));
+        const unsigned zm = zmask(z);
+        const int so = soff(z);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) q[i][k] = keep(buf_ld<0>(rc, ro[i], so), zm);
+        for (int i = 0; i < RPT; ++i) q[i][k] = keep(buf_ld<0>(rc, rr[i], so), zm);
     }
 
     struct Slot {
@@ -202,8 +217,8 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     Slot S[NS];
     auto load = [&](int z, Slot &T) {
         const int zf = z + R;
-        const unsigned fm = zf < g.Z ? ~0u : 0u;
-        const int so = soff(z), sf = soff(min(zf, zt - 1));
+        const unsigned fm = zmask(zf);
+        const int so = soff(z), sf = soff(zf);
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
         // (A, B) by squared layer distance (entry 0 is (1, 1)); skipped on interior tile planes
         if (!inner_xy || ez > 0) {
@@ -215,7 +230,7 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            T.f[i] = keep(buf_ld<0>(rc, ro[i], sf), fm);
+            T.f[i] = keep(buf_ld<0>(rc, rr[i], sf), fm);
             T.p[i] = buf_ld<NT>(rn, ro[i], so);
             T.k[i] = buf_ld<NT>(rk, ro[i], so);
             if constexpr (MODE == MODE_IMAGE) {
@@ -265,7 +280,8 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
                     }
 #pragma unroll
                     for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[lx][ly + j] + T[lx][ly - j], lap);
-                    const float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, c, W.p[i]);
+                    float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, c, W.p[i]);
+                    if (rdir[i] || zdir(z)) out = 0.0f;     // held by a Dirichlet condition
                     buf_st<NT>(out, rn, ro[i], so);
                     if constexpr (MODE == MODE_STORE) buf_st<NT>(W.k[i] * lap, rs, ro[i], so);
                     if constexpr (MODE == MODE_IMAGE)

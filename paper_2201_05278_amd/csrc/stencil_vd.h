@@ -71,9 +71,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const int64_t sz = int64_t(g.px) * g.py;
     const bool yin = y < g.Y;
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
-    // z window: planes zw .. zt - 1 (the queue reaches 2R - 1 planes ahead)
-    const int zw = max(zb - 2 * R + 1, 0);
-    const int zt = min(ze + 2 * R - 1, g.Z);
+    // z window: planes zw .. zt - 1 (the queue reaches 2R - 1 planes ahead; planes
+    // off the grid lie in the stored halo and hold mirror ghosts or are masked)
+    const int zw = zb - 2 * R + 1;
+    const int zt = ze + 2 * R - 1;
     const int pb = int(sz) * 4;
     const uint32_t wbytes = uint32_t(zt - zw) * uint32_t(pb);
     const int64_t w0 = g.base + int64_t(zw) * sz;
@@ -90,7 +91,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     auto fsoff = [&](int z) -> int { return (z - fw) * pb; };
     const auto rk = buf_res(P.K + w0, wbytes);
     const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
-    auto soff = [&](int z) -> int { return (clampi(z, zw, zt - 1) - zw) * pb; };
+    auto soff = [&](int z) -> int { return (z - zw) * pb; };
+    auto zmask = [&](int z) -> unsigned {
+        return axis_read(z, g.Z, P.bcm[0][0], P.bcm[0][1], P.gh) ? ~0u : 0u;
+    };
     auto keep = [](float v, unsigned m) -> float {
         return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m);
     };
@@ -100,17 +104,27 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     auto off = [&](int x, int yy) -> int {
         return (x >= 0 && x < g.X && yy >= 0 && yy < g.Y) ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
+    // wavefield reads: also mirror ghosts within the stored halo
+    auto roff = [&](int x, int yy) -> int {
+        const bool ok = axis_read(x, g.X, P.bcm[1][0], P.bcm[1][1], P.gh) &&
+                        axis_read(yy, g.Y, P.bcm[2][0], P.bcm[2][1], P.gh);
+        return ok ? (g.xy0 + x * g.py + yy) * 4 : kOut;
+    };
     auto foff = [&](int x, int yy) -> int {
         const bool ok = (NDIM == 2 || (x >= -R && x <= g.X + R - 2)) && yy >= -R && yy <= g.Y + R - 2;
         return ok ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
 
-    int ro[RPT], ex2[RPT];
+    int ro[RPT], rr[RPT], ex2[RPT];
+    bool rdir[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         const bool in = yin && x < g.X;
         ro[i] = off(x, y);
+        rr[i] = roff(x, y);
+        rdir[i] = axis_dirichlet(x, g.X, P.bcm[1][0], P.bcm[1][1]) ||
+                  axis_dirichlet(y, g.Y, P.bcm[2][0], P.bcm[2][1]);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = in ? ex * ex + ey * ey : 0;
     }
@@ -120,7 +134,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const int hr = wave + s * NW;
         const bool ok = hr < 2 * HX;
         const int x = (hr < HX) ? x0 - HX + hr : x0 + TX + hr - HX;
-        hxo[s] = ok ? off(x, y) : kOut;
+        hxo[s] = ok ? roff(x, y) : kOut;
         hxrow[s] = !ok ? LX : (hr < HX) ? hr : TX + hr;
     }
     int hyo[YHN], hyrow[YHN], hycol[YHN];
@@ -131,7 +145,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const int row = e / (2 * H), c = e % (2 * H);
         const int yy = (c < H) ? y0 - H + c : y0 + 64 + c - H;
         const int x = x0 + row;
-        hyo[s] = ok ? off(x, yy) : kOut;
+        hyo[s] = ok ? roff(x, yy) : kOut;
         hyrow[s] = ok ? HX + row : LX;
         hycol[s] = (c < H) ? c : 64 + c;
     }
@@ -165,10 +179,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
 #pragma unroll
     for (int k = 0; k < 2 * R - 1; ++k) {
         const int z = zs + k;
-        const unsigned m = (z >= 0 && z < g.Z) ? ~0u : 0u;
+        const unsigned m = zmask(z);
         const int so = soff(z);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) pq[i][k] = keep(buf_ld<0>(rc, ro[i], so), m);
+        for (int i = 0; i < RPT; ++i) pq[i][k] = keep(buf_ld<0>(rc, rr[i], so), m);
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
@@ -185,11 +199,11 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     // of p and the x / y face buoyancies of the thread's face items
     auto load = [&](int z, Slot &L) {
         const int zf = z + 2 * R - 1;
-        const unsigned mf = zf < g.Z ? ~0u : 0u;
+        const unsigned mf = zmask(zf);
         const int sf = soff(zf), sfz = fsoff(z + R - 1);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            L.fp[i] = keep(buf_ld<0>(rc, ro[i], sf), mf);
+            L.fp[i] = keep(buf_ld<0>(rc, rr[i], sf), mf);
             L.fz[i] = buf_ld<NT>(rfz, ro[i], sfz);
         }
         if (z < zb) return;
@@ -273,7 +287,8 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
                     dys = fmaf(P.sy[j], sfy[rr][lane + R + j - 1] - sfy[rr][lane + R - j], dys);
                 }
                 const float lap = dzs + dxs + dys;
-                const float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, pq[i][u % Q], W.p[i]);
+                float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, pq[i][u % Q], W.p[i]);
+                if (rdir[i] || axis_dirichlet(z, g.Z, P.bcm[0][0], P.bcm[0][1])) out = 0.0f;
                 buf_st<NT>(out, rn, ro[i], so);
             }
         }
@@ -319,14 +334,24 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
     float *nxt = P.nxt + g.base;
     const float *km = P.K + g.base;
 
-    unsigned roff[RPT], rroff[RPT];
-    bool rin[RPT];
+    // wavefield reads: grid nodes and mirror ghosts within the stored halo
+    auto pread = [&](int x, int yy) -> bool {
+        return axis_read(x, g.X, P.bcm[1][0], P.bcm[1][1], P.gh) &&
+               axis_read(yy, g.Y, P.bcm[2][0], P.bcm[2][1], P.gh);
+    };
+    auto zread = [&](int z) -> bool { return axis_read(z, g.Z, P.bcm[0][0], P.bcm[0][1], P.gh); };
+    unsigned roff[RPT], rroff[RPT], rpo[RPT];
+    bool rin[RPT], rp[RPT], rdir[RPT];
     int ex2[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int x = x0 + wave * RPT + i;
         rin[i] = yin && x < g.X;
         roff[i] = rin[i] ? off(x, y) : 0u;
+        rp[i] = pread(x, y);
+        rpo[i] = rp[i] ? off(x, y) : 0u;
+        rdir[i] = axis_dirichlet(x, g.X, P.bcm[1][0], P.bcm[1][1]) ||
+                  axis_dirichlet(y, g.Y, P.bcm[2][0], P.bcm[2][1]);
         rroff[i] = off(clampi(x, 0, g.X - 1), yc);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = ex * ex + ey * ey;
@@ -339,7 +364,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         const int hr = wave + s * NW;
         hxok[s] = hr < 2 * R;
         const int x = (hr < R) ? x0 - R + hr : x0 + TX + hr - R;
-        hxin[s] = hxok[s] && yin && x >= 0 && x < g.X;
+        hxin[s] = hxok[s] && pread(x, y);
         hxrow[s] = (hr < R) ? hr : TX + hr;
         hxo[s] = hxin[s] ? off(x, y) : 0u;
         hxro[s] = off(clampi(x, 0, g.X - 1), yc);
@@ -354,7 +379,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         const int row = e / (2 * R), c = e % (2 * R);
         const int yy = (c < R) ? y0 - R + c : y0 + 64 + c - R;
         const int x = x0 + row;
-        hyin[s] = hyok[s] && x < g.X && yy >= 0 && yy < g.Y;
+        hyin[s] = hyok[s] && pread(x, yy);
         hyrow[s] = HXR + row;
         hycol[s] = (c < R) ? c : 64 + c;
         hyo[s] = hyin[s] ? off(x, yy) : 0u;
@@ -367,7 +392,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 #pragma unroll
         for (int k = 0; k < 2 * R; ++k) {
             const int z = zb - R + k;
-            q[i][k] = (rin[i] && z >= 0 && z < g.Z) ? (cur + int64_t(z) * sz)[roff[i]] : 0.0f;
+            q[i][k] = (rp[i] && zread(z)) ? (cur + int64_t(z) * sz)[rpo[i]] : 0.0f;
             qr[i][k] = (rm + int64_t(clampi(z, 0, g.Z - 1)) * sz)[rroff[i]];
         }
 
@@ -379,7 +404,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         const int64_t zo = int64_t(z) * sz;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            nf[i] = (rin[i] && zf < g.Z) ? cur[roff[i] + int64_t(zf) * sz] : 0.0f;
+            nf[i] = (rp[i] && zread(zf)) ? cur[rpo[i] + int64_t(zf) * sz] : 0.0f;
             nfr[i] = rm[rroff[i] + int64_t(min(zf, g.Z - 1)) * sz];
             np_[i] = rin[i] ? ld_stream<NT>(nxt + zo + roff[i]) : 0.0f;
             nk[i] = rin[i] ? ld_stream<NT>(km + zo + roff[i]) : 0.0f;
@@ -479,7 +504,8 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
             }
             const float grad = fmaf(drz, dpz, fmaf(drx, dpx, dry * dpy));
             const float Lp = lap - grad / qr[i][R];
-            const float out = pa[i] * fmaf(pk[i], Lp, 2.0f * c) - pb[i] * pp[i];
+            float out = pa[i] * fmaf(pk[i], Lp, 2.0f * c) - pb[i] * pp[i];
+            if (rdir[i] || axis_dirichlet(z, g.Z, P.bcm[0][0], P.bcm[0][1])) out = 0.0f;
             if (rin[i]) st_stream<NT>(out, nxt + int64_t(z) * sz + roff[i]);
         }
         buf ^= 1;

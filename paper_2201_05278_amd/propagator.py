@@ -65,7 +65,7 @@ class Propagator:
     """One plan: grid, scheme, time axis, absorbing layer, geometry, model."""
 
     def __init__(self, n, h, space_order, dt, nsteps, scheme="const", nbl=0, alpha=0.001,
-                 power=3.0, device="cuda"):
+                 power=3.0, device="cuda", bc=None):
         ndim = len(n)
         prob = L.Problem()
         prob.ndim = ndim
@@ -77,6 +77,10 @@ class Propagator:
         for i, (a, b) in enumerate(_pairs(nbl, ndim)):
             prob.nbl[i][0] = a
             prob.nbl[i][1] = b
+        if bc is not None:              # per axis (low, high): "none", "dirichlet" or "neumann"
+            for i, (a, b) in enumerate(bc):
+                prob.bc[i][0] = L.BCS[a]
+                prob.bc[i][1] = L.BCS[b]
         prob.damp_alpha = float(alpha)
         prob.damp_power = float(power)
         prob.dt = float(dt)

@@ -115,15 +115,36 @@ def test_invalid_problems_refused():
     Propagator((4, 2000, 2000), (1.0,) * 3, 8, 1e-4, 5, nbl=0)
 
 
-def test_mirror_ghosts_refused():
+def test_mirror_ghost_contract():
+    # Dirichlet / Neumann sides are accepted for the forward ...
+    prop = Propagator((20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, nbl=2,
+                      bc=[("dirichlet", "neumann"), ("none", "dirichlet"), ("neumann", "none")])
+    # ... but not by the adjoint, batches, wave tiles or two-step sweeps
+    io = L.AdjIO()
+    st = L.lib().sw_adjoint(prop._plan, ctypes.byref(io), None)
+    assert L.STATUS[st] == "SW_ERR_UNSUPPORTED"
+    assert b"ghost" in L.lib().sw_last_error()
+    plans = (ctypes.c_void_p * 1)(prop._plan.value)
+    out = ctypes.c_void_p()
+    st = L.lib().sw_batch_create(1, plans, ctypes.byref(out))
+    assert L.STATUS[st] == "SW_ERR_UNSUPPORTED"
+    _expect("SW_ERR_UNSUPPORTED", prop.set_tiling, 16, 4, wt=1)
+    _expect("SW_ERR_UNSUPPORTED", prop.set_tiling, ts=2)
+    prop.set_tiling(16, 8)
+    # an axis shorter than the mirror depth plus one, and unknown conditions
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (3, 20), (10.0, 10.0), 8, 1e-3, 5, nbl=0,
+            bc=[("dirichlet", "none"), ("none", "none")])
+    Propagator((5, 20), (10.0, 10.0), 8, 1e-3, 5, nbl=0, bc=[("dirichlet", "none"), ("none", "none")])
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (7, 20), (10.0, 10.0), 8, 1e-3, 5, scheme="vd_staggered",
+            nbl=0, bc=[("neumann", "none"), ("none", "none")])
     prob = L.Problem()
     prob.ndim, prob.space_order, prob.dt, prob.nsteps = 2, 4, 1e-3, 5
     prob.n[0] = prob.n[1] = 20
     prob.h[0] = prob.h[1] = 1.0
-    prob.bc[0][0] = 1
+    prob.bc[0][0] = 7
     h = ctypes.c_void_p()
     st = L.lib().sw_plan_create(ctypes.byref(prob), ctypes.byref(h))
-    assert L.STATUS[st] == "SW_ERR_UNSUPPORTED"
+    assert L.STATUS[st] == "SW_ERR_ARG"
 
 
 def test_points_outside_domain_refused():
