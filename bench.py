@@ -22,6 +22,7 @@ the fused absorbing layer, source injection and receiver recording.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --profile-pass     (5 forward steps + a 1 GiB copy, for counters)
+       python bench.py --paper-shapes     (whole runs at the paper's Table 2 / 3 shapes)
 """
 import argparse
 import json
@@ -146,6 +147,61 @@ def profile_pass(args):
     print("profile pass done: 5 steps of the 592^3 forward, 1 GiB copy", flush=True)
 
 
+# The paper's benchmark shapes ("Performance evaluation", Tables 2 and 3), its
+# times in seconds for the whole run (FP64, host-device transfers included)
+# on its fastest GPU back-end per order, for context only.
+PAPER_SHAPES = [
+    # name, physical n, h, layer per side, tf, c_max, [(order, steps, paper best s)]
+    ("marmousi2-shaped 2D", (351, 1701), 10.0, [(0, 70), (70, 70)], 2.0, 4700.0,
+     [(2, 1331, 0.36), (4, 1537, 0.43), (8, 1696, 0.47)]),
+    ("overthrust-shaped 3D", (207, 801, 801), 20.0, [(0, 0), (0, 0), (0, 0)], 4.0, 6000.0,
+     [(2, 2080, 28.30), (4, 2401, 40.36), (8, 2651, 63.12)]),
+]
+
+
+def paper_shapes():
+    """Whole runs at the paper's grid shapes and step counts (dt at the
+    stability limit, as its counts imply), synthetic layered models reaching
+    its c_max, one source and 101 receivers; one JSON line per run."""
+    import torch
+    from paper_2201_05278_amd import Propagator, critical_dt, ricker
+    for name, n, h, nbl, tf, cmax, orders in PAPER_SHAPES:
+        rng = np.random.default_rng(7)
+        nd = len(n)
+        speeds = np.linspace(1500.0, cmax, 6)
+        vel = np.empty(n, dtype=np.float32)
+        edges = np.linspace(0, n[0], len(speeds) + 1).round().astype(int)
+        for k, v in enumerate(speeds):
+            vel[edges[k]:edges[k + 1]] = v
+        vel = np.minimum(vel + rng.normal(0.0, 20.0, n).astype(np.float32), cmax)
+        ext = [h * (k - 1) for k in n]
+        src = [[2 * h] + [e / 2 for e in ext[1:]]]
+        rec = [[h] + [e * (i / 100.0) for e in ext[1:2]] + ([ext[2] / 2] if nd == 3 else []) for i in range(101)]
+        for so, nt, paper_s in orders:
+            dt = critical_dt((h,) * nd, so, cmax)
+            prop = Propagator(n, (h,) * nd, so, dt, nt, nbl=[list(p) for p in nbl])
+            prop.set_sources(src, "linear")
+            prop.set_receivers(rec, "linear")
+            prop.prepare(torch.from_numpy(vel).cuda(), cmax=cmax)
+            wav = ricker(10.0, dt, nt).reshape(-1, 1).cuda()
+            fields = (prop.new_field(), prop.new_field())
+            traces = torch.zeros((nt, len(rec)), dtype=torch.float32, device="cuda")
+            # the whole time loop as one HIP graph: captured by the first call, replayed
+            prop.forward(wav, fields=fields, traces=traces, use_graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prop.forward(wav, fields=fields, traces=traces, use_graph=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            nodes = float(np.prod([k + a + b for k, (a, b) in zip(n, nbl)]))
+            print(json.dumps({"shape": name, "nodes": int(nodes), "space_order": so, "steps": nt,
+                              "seconds": round(el, 4), "gpts": round(nodes * nt / el / 1e9, 2),
+                              "paper_best_seconds": paper_s,
+                              "paper_best_gpts": round(nodes * nt / paper_s / 1e9, 3)}), flush=True)
+            del prop
+            torch.cuda.empty_cache()
+
+
 def cpu_baseline(wl, dt, steps):
     """FP64 oracle, constant density, first `steps` steps of the workload."""
     import oracle
@@ -181,6 +237,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "simwave_tune.json"))
     ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="whole runs at the paper's benchmark shapes instead of the headline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -194,6 +252,9 @@ def main():
     torch.cuda.set_device(0)
     if args.profile_pass:
         profile_pass(args)
+        return
+    if args.paper_shapes:
+        paper_shapes()
         return
     K, W = args.steps, args.warmup
     log(f"bench: building the smooth_3d model, n = {args.n}")
