@@ -259,7 +259,7 @@ sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
 
 /* Stencil tiling of a plan.  Results never depend on it.
  *   tx, nw  rows per block and waves per block.  3D constant density:
- *           block tiles (16,4), (8,4), (32,8), (16,8), (8,8), or with wt = 1
+ *           block tiles (16,4), (8,4), (32,8), (16,8), (8,8), (24,8), or with wt = 1
  *           wave tiles (16,4), (32,4), (4,1), (8,1), (16,2) (each wave owns
  *           tx / nw rows); 3D variable density: (16,8), (8,8), (8,4), (16,4);
  *           2D grids: fixed.  0, 0: default.
@@ -275,9 +275,14 @@ sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
  *           and columns around the tile; the tile is tx rows x (64 - 2R)
  *           columns; shapes (8,4), (16,8), (8,8), (16,4) where the register
  *           queues fit: (tx/nw)(5R+5) + ceil(2R/nw)(3R+3) <= 95, so up to R = 7).  Takes
- *           effect when sw_fwd_io.field2 is given. */
+ *           effect when sw_fwd_io.field2 is given.
+ *   occ     resident blocks per CU at most, for single-step block tiles: the
+ *           launch reserves 160 KiB / occ of LDS per block, so that fewer
+ *           z streams share each L2 (3 .. 6; 0: no cap; -1: default).  The
+ *           cap only lowers occupancy; where registers or LDS already allow
+ *           fewer blocks it has no effect.  Other values: SW_ERR_ARG. */
 typedef struct sw_tiling {
-    int32_t tx, nw, zc, nt, pf, wt, ts;
+    int32_t tx, nw, zc, nt, pf, wt, ts, occ;
 } sw_tiling;
 
 /* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan. */

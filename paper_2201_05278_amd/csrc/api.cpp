@@ -107,9 +107,26 @@ int default_zc(const sw_plan *p, int tx, int64_t want, int ts)
     return std::max(zc, std::min(p->dims[0], 4 * p->r));
 }
 
+// Default constant-density block tile and resident-block cap by radius, from a
+// sweep of the forward stencil at 592^3 over space orders 2 .. 16: short
+// stencils stream fastest with 8x4 tiles held to 4 blocks per CU (fewer z
+// streams per L2), medium ones with 24x8 tiles, long ones with 8x4 or 16x4
+// tiles whose register queues leave few blocks per CU anyway.
+struct ConstDefault {
+    int tx, nw, occ;
+};
+static ConstDefault const_default(int r)
+{
+    if (r <= 2) return {8, 4, 4};
+    if (r <= 5) return {24, 8, 0};
+    if (r == 6) return {16, 4, 3};
+    return {8, 4, 0};
+}
+
 Tiling choose_tiling(const sw_plan *p)
 {
     Tiling t{};
+    int def_occ = 0;
     if (p->ndim == 2) {
         t.tx = 1;
         t.nw = 1;
@@ -132,16 +149,21 @@ Tiling choose_tiling(const sw_plan *p)
         t.nw = tb_shape_ok(p->r, 8, 4) ? 4 : 8;
         t.ts = 2;
     } else {
-        t.tx = 8;
-        t.nw = 4;
+        const ConstDefault d = const_default(p->r);
+        t.tx = d.tx;
+        t.nw = d.nw;
+        def_occ = d.occ;
     }
     if (t.ts == 0) t.ts = 1;
-    // z chunks of about 74 planes (fewer if the grid has few tiles per plane)
+    // z chunks of about 74 planes (fewer if the grid has few tiles per plane:
+    // about 16384 waves in 3D)
     t.zc = p->tile_zc ? std::min(p->tile_zc, p->dims[0])
                       : std::min(std::min(74, p->dims[0]),
-                                 default_zc(p, t.tx, p->ndim == 2 ? 1024 : 4096, t.ts));
+                                 default_zc(p, t.tx, p->ndim == 2 ? 1024 : 16384 / t.nw, t.ts));
     t.nt = p->tile_nt < 0 ? kDefaultNT : p->tile_nt;
     t.pf = p->tile_pf ? p->tile_pf : kDefaultPF;
+    // the occupancy cap applies to single-step block tiles
+    t.occ = (t.wt || t.ts == 2) ? 0 : (p->tile_occ < 0 ? def_occ : p->tile_occ);
     return t;
 }
 
@@ -388,9 +410,11 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
 {
     set_error("");
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
-    sw_tiling d{0, 0, 0, -1, 0, 0, 0};
+    sw_tiling d{0, 0, 0, -1, 0, 0, 0, -1};
     if (t) d = *t;
     if (d.zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
+    if (d.occ < -1 || d.occ == 1 || d.occ == 2 || d.occ > 6)
+        return fail(SW_ERR_ARG, "occ must be -1 (default), 0 (no cap) or 3 .. 6");
     if (d.ts < 0 || d.ts > 2) return fail(SW_ERR_ARG, "ts must be 0, 1 or 2");
     if (d.ts == 2) {
         if (p->ndim != 3 || p->prob.scheme != SW_CONST)
@@ -420,6 +444,7 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
     p->tile_pf = d.pf;
     p->tile_wt = d.wt ? 1 : 0;
     p->tile_ts = d.ts;
+    p->tile_occ = d.occ;
     if (p->graph_exec) {
         (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
         p->graph_exec = nullptr;
@@ -432,7 +457,7 @@ sw_status sw_plan_get_tiling(const sw_plan *p, sw_tiling *out)
     set_error("");
     if (!p || !out) return fail(SW_ERR_ARG, "NULL argument");
     const Tiling t = choose_tiling(p);
-    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt, t.ts};
+    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt, t.ts, t.occ};
     return SW_OK;
 }
 

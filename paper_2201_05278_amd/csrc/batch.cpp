@@ -335,7 +335,8 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     auto it = cache.find(key);
     if (it != cache.end()) {
         auto &v = it->second;
-        const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"], v["ts"]};
+        const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"], v["ts"],
+                          v.count("occ") ? v["occ"] : -1};
         return sw_plan_set_tiling(p, &t);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -357,7 +358,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     SW_HIP(hipEventCreate(&e0));
     SW_HIP(hipEventCreate(&e1));
     float best = std::numeric_limits<float>::max();
-    sw_tiling best_t{0, 0, 0, -1, 0, 0, 0};
+    sw_tiling best_t{0, 0, 0, -1, 0, 0, 0, -1};
     StencilParams P;
     fill_params(p, io->workspace, P);
     P.cur = io->field[0];
@@ -367,7 +368,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
             for (int nt : {0, 1})
                 for (int pf : {1, 2}) {
                 if ((!const3 || sh.wt || sh.ts == 2) && pf == 2) continue;
-                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts};
+                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts, -1};
                 st = sw_plan_set_tiling(p, &cand);
                 if (st != SW_OK) continue;
                 // per-step time: single sweeps, or two-step sweeps over half as many launches
@@ -394,7 +395,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     st = sw_plan_set_tiling(p, &best_t);
     if (st != SW_OK) return st;
     cache[key] = {{"tx", best_t.tx}, {"nw", best_t.nw}, {"zc", best_t.zc}, {"nt", best_t.nt},
-                  {"pf", best_t.pf}, {"wt", best_t.wt}, {"ts", best_t.ts}};
+                  {"pf", best_t.pf}, {"wt", best_t.wt}, {"ts", best_t.ts}, {"occ", best_t.occ}};
     write_cache(cache_path, cache);
     return SW_OK;
 }

@@ -78,7 +78,34 @@ struct Tiling {
     int pf;                 // planes of loads kept in flight ahead of the update (1 or 2)
     int wt;                 // 1: wave tiles (each wave owns tx / nw rows, no block barrier)
     int ts;                 // time steps per sweep (1, or 2 for the two-step constant-density sweep)
+    int occ;                // resident blocks per CU at most (0: as registers and LDS allow; else 3..6)
 };
+
+// Dynamic LDS bytes that hold a kernel with `static_lds` bytes of its own to
+// at most `occ` resident blocks per CU (0 = no cap).  A CU has 160 KiB of LDS;
+// each block is given 160 KiB / occ in total, rounded down to a multiple of
+// 2560 bytes (a multiple of every LDS allocation granule), which leaves no
+// room for block occ + 1 for occ <= 6.  Where the static LDS alone already
+// exceeds that share the kernel is left as it is.
+inline unsigned occ_pad_bytes(int occ, int static_lds)
+{
+    if (occ <= 0) return 0;
+    const int share = (160 * 1024 / occ) / 2560 * 2560;
+    return share > static_lds ? unsigned(share - static_lds) : 0u;
+}
+
+// Static LDS bytes of kernel KERN (read once per kernel and cached: one
+// instantiation, and so one cached value, per kernel).
+template <auto KERN>
+int static_lds_of()
+{
+    static const int bytes = [] {
+        hipFuncAttributes a{};
+        return hipFuncGetAttributes(&a, reinterpret_cast<const void *>(KERN)) == hipSuccess
+                   ? int(a.sharedSizeBytes) : 0;
+    }();
+    return bytes;
+}
 
 // Second output and injection of a two-step sweep (P.cur = p^n, P.nxt = p^{n-1}
 // read only): p^{n+1} -> out1, p^{n+2} -> out2; inj[which * nuniq + u] is added

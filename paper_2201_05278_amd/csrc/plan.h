@@ -91,7 +91,8 @@ struct sw_plan {
     bool prepared = false;
     void *prepared_ws = nullptr;
     // stencil tiling chosen by sw_plan_set_tiling / sw_plan_autotune (tx == 0: default)
-    int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = -1, tile_pf = 0, tile_wt = 0, tile_ts = 0;
+    int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = -1, tile_pf = 0, tile_wt = 0, tile_ts = 0,
+        tile_occ = -1;
     // cached HIP graph of a forward run, captured on a private stream
     void *graph_exec = nullptr;
     void *capture_stream = nullptr;

@@ -523,14 +523,21 @@ __global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__
 // Tile shapes (rows, waves) instantiated for 3D grids; 2D grids use (1, 1).
 #define SW_CONST_SHAPES(X) X(16, 4) X(8, 4) X(32, 8) X(16, 8) X(8, 8) X(24, 8)
 
-template <int R, int NDIM, int TX, int NW, int NT, int PF>
-hipError_t launch_const_shape(int mode, StencilParams &P, hipStream_t s)
+template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
+void launch_const_mode(int occ, StencilParams &P, hipStream_t s)
 {
-    const dim3 grid(P.ntx * P.nty * P.nzc), block(64 * NW);
+    constexpr auto kern = k_const<R, NDIM, TX, NW, MODE, NT, PF>;
+    const unsigned pad = occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u;
+    hipLaunchKernelGGL(kern, dim3(P.ntx * P.nty * P.nzc), dim3(64 * NW), pad, s, P);
+}
+
+template <int R, int NDIM, int TX, int NW, int NT, int PF>
+hipError_t launch_const_shape(int mode, int occ, StencilParams &P, hipStream_t s)
+{
     switch (mode) {
-    case MODE_FWD: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_FWD, NT, PF>), grid, block, 0, s, P); break;
-    case MODE_STORE: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_STORE, NT, PF>), grid, block, 0, s, P); break;
-    default: hipLaunchKernelGGL((k_const<R, NDIM, TX, NW, MODE_IMAGE, NT, PF>), grid, block, 0, s, P); break;
+    case MODE_FWD: launch_const_mode<R, NDIM, TX, NW, MODE_FWD, NT, PF>(occ, P, s); break;
+    case MODE_STORE: launch_const_mode<R, NDIM, TX, NW, MODE_STORE, NT, PF>(occ, P, s); break;
+    default: launch_const_mode<R, NDIM, TX, NW, MODE_IMAGE, NT, PF>(occ, P, s); break;
     }
     return hipGetLastError();
 }
@@ -553,7 +560,7 @@ hipError_t launch_wave_shape(int mode, StencilParams &P, hipStream_t s)
 template <int R, int NT, int PF>
 hipError_t launch_const_v(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    if (ndim == 2) return launch_const_shape<R, 2, 1, 1, NT, PF>(mode, P, s);
+    if (ndim == 2) return launch_const_shape<R, 2, 1, 1, NT, PF>(mode, t.occ, P, s);
     if (t.wt) {
 #define SW_X(RWV, NWV) \
         if (t.tx == RWV * NWV && t.nw == NWV) return launch_wave_shape<R, 3, RWV, NWV, NT>(mode, P, s);
@@ -562,7 +569,7 @@ hipError_t launch_const_v(int ndim, int mode, const Tiling &t, StencilParams &P,
         return hipErrorInvalidValue;
     }
 #define SW_X(TXV, NWV) \
-    if (t.tx == TXV && t.nw == NWV) return launch_const_shape<R, 3, TXV, NWV, NT, PF>(mode, P, s);
+    if (t.tx == TXV && t.nw == NWV) return launch_const_shape<R, 3, TXV, NWV, NT, PF>(mode, t.occ, P, s);
     SW_CONST_SHAPES(SW_X)
 #undef SW_X
     return hipErrorInvalidValue;

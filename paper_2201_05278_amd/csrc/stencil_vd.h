@@ -522,21 +522,26 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 // Tile shapes (rows, waves) of the variable-density kernels in 3D; 2D uses (1, 1).
 #define SW_VD_SHAPES(X) X(16, 8) X(8, 8) X(8, 4) X(16, 4)
 
+template <int R, int NDIM, int TX, int NW, int NT>
+hipError_t launch_vd_shape(int scheme, int occ, StencilParams &P, hipStream_t s)
+{
+    const dim3 grid(P.ntx * P.nty * P.nzc), block(64 * NW);
+    if (scheme == 1) {
+        constexpr auto kern = k_stag<R, NDIM, TX, NW, NT>;
+        hipLaunchKernelGGL(kern, grid, block, occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u, s, P);
+    } else {
+        constexpr auto kern = k_cent<R, NDIM, TX, NW, NT>;
+        hipLaunchKernelGGL(kern, grid, block, occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u, s, P);
+    }
+    return hipGetLastError();
+}
+
 template <int R, int NT>
 hipError_t launch_vd_nt(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    const dim3 grid(P.ntx * P.nty * P.nzc);
-    if (ndim == 2) {
-        if (scheme == 1) hipLaunchKernelGGL((k_stag<R, 2, 1, 1, NT>), grid, dim3(64), 0, s, P);
-        else hipLaunchKernelGGL((k_cent<R, 2, 1, 1, NT>), grid, dim3(64), 0, s, P);
-        return hipGetLastError();
-    }
-#define SW_X(TXV, NWV)                                                                             \
-    if (t.tx == TXV && t.nw == NWV) {                                                              \
-        if (scheme == 1) hipLaunchKernelGGL((k_stag<R, 3, TXV, NWV, NT>), grid, dim3(64 * NWV), 0, s, P); \
-        else hipLaunchKernelGGL((k_cent<R, 3, TXV, NWV, NT>), grid, dim3(64 * NWV), 0, s, P);    \
-        return hipGetLastError();                                                                  \
-    }
+    if (ndim == 2) return launch_vd_shape<R, 2, 1, 1, NT>(scheme, t.occ, P, s);
+#define SW_X(TXV, NWV) \
+    if (t.tx == TXV && t.nw == NWV) return launch_vd_shape<R, 3, TXV, NWV, NT>(scheme, t.occ, P, s);
     SW_VD_SHAPES(SW_X)
 #undef SW_X
     return hipErrorInvalidValue;

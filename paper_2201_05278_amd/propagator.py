@@ -188,10 +188,11 @@ class Propagator:
         return self
 
     # ---- tiling -------------------------------------------------------------
-    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0, ts=0):
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0, ts=0, occ=-1):
         """Stencil tile shape, z-chunk length, cache policy, prefetch distance,
-        wave-tile mode and time steps per sweep (0 / -1: default)."""
-        t = L.Tiling(tx, nw, zc, nt, pf, wt, ts)
+        wave-tile mode, time steps per sweep and resident-block cap per CU
+        (0 / -1: default; occ=0: no cap)."""
+        t = L.Tiling(tx, nw, zc, nt, pf, wt, ts, occ)
         L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, ctypes.byref(t)))
 
     @property
@@ -243,6 +244,9 @@ class Propagator:
             raise RuntimeError("prepare() must be called after the geometry is set")
         lay = self.layout
         nrun = self.nsteps - step0 if nsteps_run is None else int(nsteps_run)
+        # drop the previous call's buffers first, so that the allocator can
+        # hand them out again (work queued on the stream keeps its order)
+        self._keep = None
         if fields is None:
             fields = (self.new_field(), self.new_field())
         if lay.nsrc:
@@ -286,6 +290,7 @@ class Propagator:
         lay = self.layout
         fe = lay.field_elems
         dev = self.device
+        self._keep_adj = None          # the previous call's scratch can be reused
         work = [torch.empty(fe, dtype=torch.float32, device=dev) for _ in range(4)]
         segment = torch.empty((checkpoint_every, fe), dtype=torch.float32, device=dev)
         grad_m = torch.empty(fe, dtype=torch.float32, device=dev)

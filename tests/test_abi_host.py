@@ -196,3 +196,29 @@ def test_tiling_choices_validated():
     _expect("SW_ERR_UNSUPPORTED", flat.set_tiling, ts=2)
     vd = Propagator((30, 30, 30), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered", nbl=4)
     _expect("SW_ERR_UNSUPPORTED", vd.set_tiling, ts=2)
+
+
+def test_occupancy_cap_and_default_tiles():
+    # default constant-density tiles by order, with their resident-block caps
+    expect = {2: (8, 4, 4), 4: (8, 4, 4), 6: (24, 8, 0), 8: (24, 8, 0), 10: (24, 8, 0),
+              12: (16, 4, 3), 14: (8, 4, 0), 16: (8, 4, 0)}
+    for so, (tx, nw, occ) in expect.items():
+        t = Propagator((40, 40, 40), (10.0,) * 3, so, 1e-4, 5, nbl=4).tiling
+        assert (t["tx"], t["nw"], t["occ"], t["ts"], t["wt"]) == (tx, nw, occ, 1, 0), so
+    prop = Propagator((40, 40, 40), (10.0,) * 3, 4, 1e-3, 5, nbl=4)
+    prop.set_tiling(16, 4)                        # an explicit shape has no cap by default
+    assert prop.tiling["occ"] == 0
+    for occ in (0, 3, 4, 5, 6):
+        prop.set_tiling(16, 4, occ=occ)
+        assert prop.tiling["occ"] == occ
+    for bad in (-2, 1, 2, 7, 64):
+        _expect("SW_ERR_ARG", prop.set_tiling, 16, 4, occ=bad)
+    prop.set_tiling(16, 4, wt=1, occ=4)           # wave tiles and two-step sweeps take no cap
+    assert prop.tiling["occ"] == 0
+    prop.set_tiling(ts=2, occ=4)
+    assert prop.tiling["occ"] == 0
+    prop.set_tiling()
+    assert (prop.tiling["tx"], prop.tiling["occ"]) == (8, 4)
+    vd = Propagator((40, 40, 40), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered", nbl=4)
+    vd.set_tiling(8, 4, occ=5)
+    assert vd.tiling["occ"] == 5

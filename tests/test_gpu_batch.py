@@ -31,12 +31,13 @@ def test_tilings_are_bitwise_identical():
     torch.cuda.synchronize()
     u_ref = prop.grid_view(ref.fields[ref.current]).clone()
     tr_ref = ref.traces.clone()
-    for tx, nw, zc, nt, pf, wt in [(8, 4, 0, 0, 1, 0), (32, 8, 13, 1, 2, 0), (16, 8, 100, 1, 1, 0),
-                                   (16, 4, 9, 0, 2, 0), (8, 8, 20, 1, 2, 0), (16, 4, 17, 1, 0, 1),
-                                   (4, 1, 0, 0, 0, 1), (8, 1, 31, 1, 0, 1), (24, 8, 11, 1, 1, 0),
-                                   (24, 8, 0, 0, 2, 0)]:
-        print(f"case: tiling {tx}x{nw} zc={zc} nt={nt} pf={pf} wave={wt}", flush=True)
-        prop.set_tiling(tx, nw, zc, nt, pf, wt)
+    for tx, nw, zc, nt, pf, wt, occ in [(8, 4, 0, 0, 1, 0, 0), (32, 8, 13, 1, 2, 0, 0), (16, 8, 100, 1, 1, 0, 0),
+                                        (16, 4, 9, 0, 2, 0, 0), (8, 8, 20, 1, 2, 0, 0), (16, 4, 17, 1, 0, 1, -1),
+                                        (4, 1, 0, 0, 0, 1, -1), (8, 1, 31, 1, 0, 1, -1), (24, 8, 11, 1, 1, 0, 0),
+                                        (24, 8, 0, 0, 2, 0, 0), (8, 4, 5, 1, 1, 0, 4), (16, 4, 0, 1, 2, 0, 3),
+                                        (8, 8, 7, 0, 1, 0, 6), (24, 8, 3, 1, 1, 0, 3)]:
+        print(f"case: tiling {tx}x{nw} zc={zc} nt={nt} pf={pf} wave={wt} occ={occ}", flush=True)
+        prop.set_tiling(tx, nw, zc, nt, pf, wt, occ=occ)
         r = prop.forward(wav)
         torch.cuda.synchronize()
         assert torch.equal(r.traces, tr_ref)

@@ -84,7 +84,8 @@ def test_mirror_tilings_and_graph_bitwise():
     ref, res, prop, w = _case(n, 8, [(0, 0)] * 3, bc, "const", 70, src, rec, 71)
     assert _rel(res.traces.cpu().numpy(), ref.traces) < 1e-4
     u = prop.grid_view(res.fields[res.current]).clone()
-    for tiling in [dict(tx=16, nw=8, zc=5), dict(tx=24, nw=8, zc=1), dict(tx=8, nw=8, zc=0, nt=0)]:
+    for tiling in [dict(tx=16, nw=8, zc=5), dict(tx=24, nw=8, zc=1), dict(tx=8, nw=8, zc=0, nt=0),
+                   dict(tx=8, nw=4, zc=9, occ=4)]:
         print(f"case: mirror tiling {tiling}", flush=True)
         prop.set_tiling(**tiling)
         r = prop.forward(w)

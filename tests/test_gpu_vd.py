@@ -88,9 +88,10 @@ def test_vd_tilings_are_bitwise_identical(scheme):
     torch.cuda.synchronize()
     u_ref = prop.grid_view(ref.fields[ref.current]).clone()
     tr_ref = ref.traces.clone()
-    for tx, nw, zc, nt in [(8, 8, 0, 1), (16, 8, 7, 0), (8, 4, 13, 1), (16, 4, 25, 0), (8, 4, 1, 0)]:
-        print(f"case: {scheme} tiling {tx}x{nw} zc={zc} nt={nt}", flush=True)
-        prop.set_tiling(tx, nw, zc, nt)
+    for tx, nw, zc, nt, occ in [(8, 8, 0, 1, 0), (16, 8, 7, 0, 0), (8, 4, 13, 1, 0), (16, 4, 25, 0, 0),
+                                (8, 4, 1, 0, 0), (8, 4, 9, 1, 5), (16, 4, 0, 1, 3)]:
+        print(f"case: {scheme} tiling {tx}x{nw} zc={zc} nt={nt} occ={occ}", flush=True)
+        prop.set_tiling(tx, nw, zc, nt, occ=occ)
         r = prop.forward(wav)
         torch.cuda.synchronize()
         assert torch.equal(r.traces, tr_ref)
