@@ -15,4 +15,5 @@ Modules:
 from . import coeffs, geometry, core  # noqa: F401
 from .core import (Problem, prepare, forward, gradient, gradient_checkpointed,  # noqa: F401
                    geometry_table, ricker, damping, extend, apply_L, step, step_points,
-                   injection_terms, fold_to_physical)
+                   injection_terms, fold_to_physical, gradient_vd, face_difference,
+                   midpoint_transpose, source_term)

@@ -31,6 +31,28 @@ constant density, ghost condition "none" so that L is symmetric):
       node each layer node copies.
   phi = M A mu where mu is the Lagrange multiplier of the update equation.
   The adjoint of the source map is (F^T r)_s^n = sum_x (d_s/dV) phi^{n+1}.
+
+Adjoint of the staggered variable-density forward map (velocity and density
+gradients; ghost condition "none").  With zero ghosts the half-node
+difference D+ (nodes -> faces m + 1/2, every face the divergence reads,
+m = -r .. n + r - 2 per axis) and the node difference D- satisfy D- = -(D+)^T,
+so L = -sum_i (D+_i)^T diag(b_i) D+_i is symmetric (b_i the face buoyancies).
+The update is u^{n+1} = A (2 u^n + K L u^n + M q^n) - B u^{n-1}, K = dt^2 rho c^2,
+M = dt^2 c^2, q^n the source term (d_s / dV) S_s(t_n).  Taking the Lagrange
+multiplier mu^n of step n and phi^{n+1} = K A mu^n:
+      phi^m = A (2 phi^{m+1} + K L phi^{m+1} + K P_r^T r^{m-1}) - B phi^{m+2}
+  (the forward stencil again, the residual entering with weight A K), and
+      dJ/dK      = sum_n phi^{n+1} (L u^n) / K
+      dJ/dM      = sum_n phi^{n+1} q^n / K                (source nodes only)
+      dJ/db_face = -sum_n (D+_i phi^{n+1}) (D+_i u^n)      per axis and face
+      dJ/db      = the transpose of the midpoint interpolation
+                   b_{m+1/2} = sum_j m_j (b_{m+j} + b_{m-j+1}) (indices clamped
+                   to the grid, as the forward reads b) applied to dJ/db_face
+      dJ/dc      = dJ/dK 2 dt^2 rho c + dJ/dM 2 dt^2 c
+      dJ/drho    = dJ/dK dt^2 c^2 - dJ/db / rho^2
+  each summed back from the layer onto the physical node it copies.  The paper
+  states no adjoint: this is the exact adjoint of the discrete forward map,
+  pinned by finite differences of that map.
 """
 from dataclasses import dataclass, field
 import ctypes
@@ -210,13 +232,15 @@ def apply_L(st, p):
     return out
 
 
-def inject(st, field_flat, table, amplitudes, divide_by_volume=True):
-    """field[node] += A M w (/dV) * amplitude[id] for every table entry."""
+def inject(st, field_flat, table, amplitudes, divide_by_volume=True, weight=None):
+    """field[node] += A W w (/dV) * amplitude[id] for every table entry, W = M
+    unless another multiplier field is given."""
     nodes, ids, w = table
     if len(nodes) == 0:
         return
+    W = st.M if weight is None else weight
     scale = w / st.prob.dV if divide_by_volume else w
-    np.add.at(field_flat, nodes, st.A.ravel()[nodes] * st.M.ravel()[nodes] * scale * amplitudes[ids])
+    np.add.at(field_flat, nodes, st.A.ravel()[nodes] * W.ravel()[nodes] * scale * amplitudes[ids])
 
 
 def record(field_flat, table, npts):
@@ -319,7 +343,7 @@ def adjoint_segment(st, rec, residual, history_fn, m_hi, m_lo, state, gM, src=No
         step(st, state.phi1, state.phi2)            # phi2 <- phi^m before injection
         phi = state.phi2
         flat = phi.reshape(-1)
-        inject(st, flat, rec, residual[m - 1], divide_by_volume=False)
+        inject(st, flat, rec, residual[m - 1], divide_by_volume=False, weight=st.K)
         if src is not None:
             src_adj[m - 1] = record(flat, (src[0], src[1], src[2] / prob.dV), src_adj.shape[1])
         d2u = second_difference(st, history_fn(m), history_fn(m - 1), history_fn(m - 2))
@@ -349,6 +373,87 @@ def gradient(st, rec, residual, history, src=None, nsrc=0):
     adjoint_segment(st, rec, residual, u, nsteps, 1, state, gM, src, src_adj)
     gc = fold_to_physical(prob, gM * 2.0 * prob.dt ** 2 * st.c)
     return gM, gc, src_adj
+
+
+def face_difference(st, q, axis):
+    """(D+ q)_{m+1/2} along `axis` on the faces m = -r .. n + r - 2 (array index
+    m + r), zero ghosts:  (1/h) sum_l s_l (q_{m+l} - q_{m-l+1})."""
+    prob = st.prob
+    r = prob.r
+    s = coeffs.staggered(prob.space_order)
+    g = np.moveaxis(q, axis, 0)
+    n = g.shape[0]
+    padded = np.zeros((n + 4 * r,) + g.shape[1:])
+    padded[2 * r:2 * r + n] = g                # node k at index k + 2r
+    nf = n + 2 * r - 1
+    out = np.zeros((nf,) + g.shape[1:])
+    for l in range(1, r + 1):
+        # face m sits at index t = m + r: q_{m+l} at t + r + l, q_{m-l+1} at t + r - l + 1
+        out += float(s[l]) * (padded[r + l:r + l + nf] - padded[r - l + 1:r - l + 1 + nf])
+    return np.moveaxis(out / prob.h[axis], 0, axis)
+
+
+def midpoint_transpose(st, F, axis):
+    """Transpose of the face buoyancy interpolation along `axis`: node values
+    from face values F (faces m = -r .. n + r - 2), where the forward takes
+    b_{m+1/2} = sum_j m_j (b_{m+j} + b_{m-j+1}) with node indices clamped to
+    the grid."""
+    prob = st.prob
+    r = prob.r
+    mj = coeffs.midpoint(prob.space_order)
+    Fm = np.moveaxis(F, axis, 0)
+    n = Fm.shape[0] - 2 * r + 1
+    out = np.zeros((n,) + Fm.shape[1:])
+    m = np.arange(-r, n + r - 1)
+    for j in range(1, r + 1):
+        np.add.at(out, np.clip(m + j, 0, n - 1), float(mj[j]) * Fm)
+        np.add.at(out, np.clip(m - j + 1, 0, n - 1), float(mj[j]) * Fm)
+    return np.moveaxis(out, 0, axis)
+
+
+def source_term(st, table, amplitudes):
+    """q: sum over table entries of (w / dV) amplitude[id] at each node."""
+    nodes, ids, w = table
+    q = np.zeros(int(np.prod(st.prob.N)))
+    if len(nodes):
+        np.add.at(q, nodes, (w / st.prob.dV) * amplitudes[ids])
+    return q.reshape(st.prob.N)
+
+
+def gradient_vd(st, wavelet, src, rec, residual, history):
+    """Velocity and density gradients of 1/2 sum (rec - d_obs)^2 for the
+    staggered variable-density scheme, from the stored history u^0 .. u^N:
+    (dJ/dc, dJ/drho) on the physical grid and (dJ/dK, dJ/dM, dJ/db) on the
+    extended grid."""
+    prob = st.prob
+    if prob.scheme != "vd_staggered":
+        raise ValueError("gradient_vd covers the staggered variable-density scheme")
+    if any(b != "none" for side in prob.bc for b in side):
+        raise NotImplementedError("the adjoint assumes the zero ghost condition")
+    N = prob.N
+    nsteps = len(history) - 1
+    gK = np.zeros(N)
+    gMsrc = np.zeros(N)
+    gface = [np.zeros(tuple(N[a] + (2 * prob.r - 1 if a == i else 0) for a in range(prob.ndim)))
+             for i in range(prob.ndim)]
+    state = AdjointState(N)
+    for m in range(nsteps, 0, -1):
+        step(st, state.phi1, state.phi2)           # phi2 <- phi^m before injection
+        phi = state.phi2
+        inject(st, phi.reshape(-1), rec, residual[m - 1], divide_by_volume=False, weight=st.K)
+        u = history[m - 1]                         # u^n with n = m - 1
+        gK += phi * apply_L(st, u) / st.K
+        if wavelet is not None:
+            gMsrc += phi * source_term(st, src, wavelet[m - 1]) / st.K
+        for i in range(prob.ndim):
+            gface[i] -= face_difference(st, phi, i) * face_difference(st, u, i)
+        state.phi1, state.phi2 = phi, state.phi1
+    gb = sum(midpoint_transpose(st, gface[i], i) for i in range(prob.ndim))
+    rho = 1.0 / st.aux
+    dt2 = prob.dt ** 2
+    gc_ext = gK * 2.0 * dt2 * rho * st.c + gMsrc * 2.0 * dt2 * st.c
+    grho_ext = gK * dt2 * st.c ** 2 - gb / rho ** 2
+    return (fold_to_physical(prob, gc_ext), fold_to_physical(prob, grho_ext), gK, gMsrc, gb)
 
 
 def gradient_checkpointed(st, wavelet, src, rec, nrec, residual_fn, every):

@@ -113,3 +113,104 @@ def test_checkpointed_gradient_is_bitwise_equal():
                                                  lambda tr: tr - d_obs, every=10)
     assert np.array_equal(tr2, fw.traces)
     assert np.array_equal(gM, gM2) and np.array_equal(gc, gc2)
+
+
+# ---- staggered variable-density adjoint --------------------------------------
+
+def _vd_setup(n=(24, 28), nbl=5, so=4, nt=80, seed=5, points=True):
+    h = tuple(10.0 for _ in n)
+    rng = np.random.default_rng(seed)
+    c = 1800.0 + 600.0 * rng.random(n)
+    rho = 1500.0 + 1000.0 * rng.random(n)
+    dt = 0.5 * coeffs.critical_dt(h, so, c.max())
+    prob = oracle.Problem(n=n, h=h, space_order=so, dt=dt, nsteps=nt, scheme="vd_staggered",
+                          nbl=tuple((nbl, nbl + 1) for _ in n))
+    if not points:
+        return prob, c, rho
+    if len(n) == 2:
+        src_pts, rec_pts = [(61.3, 77.7), (150.0, 190.0)], [(20.0 + 13.0 * k, 30.0 + 17.0 * k) for k in range(9)]
+    else:
+        src_pts, rec_pts = [(41.3, 47.7, 52.2)], [(10.0 + 7.0 * k, 20.0 + 5.0 * k, 15.0 + 6.0 * k) for k in range(8)]
+    src = oracle.geometry_table(prob, src_pts, "hicks")
+    rec = oracle.geometry_table(prob, rec_pts, "hicks")
+    wav = np.stack([oracle.ricker(18.0 + 3.0 * k, prob.dt, prob.nsteps) for k in range(len(src_pts))], axis=1)
+    return prob, c, rho, src, rec, len(rec_pts), wav, rng
+
+
+def _face_buoyancy(st, b, axis):
+    # b_{m+1/2} = sum_j m_j (b_{m+j} + b_{m-j+1}) on faces m = -r .. n + r - 2,
+    # node indices clamped to the grid (nearest node outside it)
+    r = st.prob.r
+    mj = coeffs.midpoint(st.prob.space_order)
+    bm = np.moveaxis(b, axis, 0)
+    n = bm.shape[0]
+    out = np.zeros((n + 2 * r - 1,) + bm.shape[1:])
+    for t, m in enumerate(range(-r, n + r - 1)):
+        for j in range(1, r + 1):
+            out[t] += float(mj[j]) * (bm[min(max(m + j, 0), n - 1)] + bm[min(max(m - j + 1, 0), n - 1)])
+    return np.moveaxis(out, 0, axis)
+
+
+@pytest.mark.parametrize("n,so", [((13, 17), 4), ((13, 17), 8), ((7, 9, 8), 6)])
+def test_staggered_operator_energy_form(n, so):
+    # <L u, v> = -sum_i <b_i D+_i u, D+_i v> over every face the divergence
+    # reads: pins the face range and D- = -(D+)^T of the half-node differences
+    # against the C operator, and makes L symmetric.
+    prob, c, rho = _vd_setup(n=n, so=so, nbl=2, nt=1, points=False)
+    st = oracle.prepare(prob, c, rho)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(prob.N)
+    v = rng.standard_normal(prob.N)
+    Lu, Lv = oracle.apply_L(st, u), oracle.apply_L(st, v)
+    energy = -sum(np.sum(_face_buoyancy(st, st.aux, i) * oracle.face_difference(st, u, i) *
+                         oracle.face_difference(st, v, i)) for i in range(prob.ndim))
+    scale = np.sum(np.abs(Lu * v))
+    assert abs(np.sum(Lu * v) - energy) < 1e-12 * scale
+    assert abs(np.sum(Lu * v) - np.sum(u * Lv)) < 1e-12 * scale
+
+
+def test_midpoint_transpose_is_adjoint_of_interpolation():
+    prob, c, rho = _vd_setup(n=(9, 11, 7), so=8, nbl=1, nt=1, points=False)
+    st = oracle.prepare(prob, c, rho)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(prob.N)
+    for i in range(3):
+        F = rng.standard_normal(_face_buoyancy(st, b, i).shape)
+        lhs = np.sum(F * _face_buoyancy(st, b, i))
+        rhs = np.sum(oracle.midpoint_transpose(st, F, i) * b)
+        assert abs(lhs - rhs) < 1e-12 * np.sum(np.abs(F))
+
+
+def _vd_misfit(prob, c, rho, src, rec, nrec, wav, d_obs):
+    st = oracle.prepare(prob, c, rho)
+    tr = oracle.forward(st, wav, src, rec, nrec).traces
+    return 0.5 * np.sum((tr - d_obs) ** 2)
+
+
+@pytest.mark.parametrize("n,nbl,so", [((24, 28), 5, 4), ((20, 22), 0, 8), ((10, 11, 12), 3, 4)])
+def test_vd_gradients_match_finite_differences(n, nbl, so):
+    prob, c, rho, src, rec, nrec, wav, rng = _vd_setup(n=n, nbl=nbl, so=so, nt=70 if len(n) == 2 else 45)
+    d_obs = oracle.forward(oracle.prepare(prob, c * (1.0 + 0.05 * rng.standard_normal(n)),
+                                          rho * (1.0 + 0.1 * rng.standard_normal(n))),
+                           wav, src, rec, nrec).traces
+    st = oracle.prepare(prob, c, rho)
+    fw = oracle.forward(st, wav, src, rec, nrec, keep_history=True)
+    gc, grho, *_ = oracle.gradient_vd(st, wav, src, rec, fw.traces - d_obs, fw.history)
+    # a random direction, and single physical nodes: a corner (its layer
+    # copies and the clamped buoyancy reads), an edge node and a node under
+    # the first source
+    dirs = [rng.standard_normal(n)]
+    for idx in [(0,) * len(n), (n[0] - 1,) + (3,) * (len(n) - 1), tuple(int(round(x / 10.0)) for x in
+                                                                         ((61.3, 77.7) if len(n) == 2 else (41.3, 47.7, 52.2)))]:
+        e = np.zeros(n)
+        e[idx] = 1.0
+        dirs.append(e)
+    for d in dirs:
+        for which, g, base in (("c", gc, c), ("rho", grho, rho)):
+            eps = 1e-6 * np.linalg.norm(base) / np.linalg.norm(d) if d.sum() != 1.0 else 1e-6 * base.mean()
+            args_p = (c + eps * d, rho) if which == "c" else (c, rho + eps * d)
+            args_m = (c - eps * d, rho) if which == "c" else (c, rho - eps * d)
+            fd = (_vd_misfit(prob, *args_p, src, rec, nrec, wav, d_obs) -
+                  _vd_misfit(prob, *args_m, src, rec, nrec, wav, d_obs)) / (2 * eps)
+            an = np.sum(g * d)
+            assert abs(fd - an) < 2e-6 * max(abs(an), 1e-3 * np.abs(g).max()), (which, fd, an)
