@@ -240,11 +240,18 @@ typedef struct sw_adj_io {
     float *field[2];          /* device work buffers (field_elems each) */
     float *adj[2];            /* device adjoint wavefield buffers (field_elems each) */
     float *segment;           /* device [ckpt_every][field_elems] recomputed
-                                 dt^2 c^2 (L u^n + source) levels */
+                                 dt^2 c^2 (L u^n + source) levels; staggered scheme:
+                                 [2][ckpt_every][field_elems], the K L u^n levels and
+                                 the levels u^n themselves */
     float *grad_m;            /* device field_elems: dJ/d(dt^2 c^2) on the extended grid
-                                 (cleared and accumulated by the call) */
+                                 (staggered scheme: dJ/dK, K = dt^2 rho c^2; cleared and
+                                 accumulated by the call) */
     float *grad_vel;          /* device [physical_nodes]: dJ/dc (written) */
     float *src_adjoint;       /* device [nsteps][nsrc] adjoint of the source map, or NULL */
+    /* staggered variable density only (ignored otherwise): */
+    float *grad_rho;          /* device [physical_nodes]: dJ/drho (written) */
+    float *vd_work;           /* device [4][field_elems] scratch: per-axis face imaging
+                                 sums and the source imaging term */
 } sw_adj_io;
 
 /* Velocity gradient of J = 1/2 sum_n sum_k (rec[n][k] - d_obs[n][k])^2 for a
@@ -254,7 +261,19 @@ typedef struct sw_adj_io {
  * the residual spread by the receiver weights; the zero-lag imaging condition
  * accumulates dJ/dM = sum_n phi^{n+1} M (L u^n + Q s^n) / M^2 with u^n
  * recomputed segment by segment from the checkpoints; dJ/dc = dJ/dM 2 dt^2 c
- * summed back from the layer onto the physical node it copies. */
+ * summed back from the layer onto the physical node it copies.
+ *
+ * Staggered variable-density plans (zero ghosts) get velocity and density
+ * gradients.  The operator L = -sum_i (D+_i)^T diag(b_i) D+_i is symmetric, so
+ * the adjoint is the same stencil with K = dt^2 rho c^2 and the residual
+ * entering with weight A K; per step n the call accumulates
+ *   dJ/dK     += phi^{n+1} K L u^n / K^2          (fused into the stencil)
+ *   dJ/db_f   -= (D+_i phi^{n+1}) (D+_i u^n)       (every face of every axis)
+ *   S         += phi^{n+1} M q^n                   (source nodes; dJ/dM = S / (K M))
+ * and then, per extended node, dJ/db by the transpose of the face buoyancy
+ * interpolation, dJ/dc = 2 dt^2 c (dJ/dK rho + dJ/dM) and
+ * dJ/drho = dJ/dK dt^2 c^2 - dJ/db / rho^2, folded onto the physical grid.
+ * The centred variable-density scheme and mirror ghosts: SW_ERR_UNSUPPORTED. */
 sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
 
 /* Stencil tiling of a plan.  Results never depend on it.

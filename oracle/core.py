@@ -50,7 +50,9 @@ multiplier mu^n of step n and phi^{n+1} = K A mu^n:
                    to the grid, as the forward reads b) applied to dJ/db_face
       dJ/dc      = dJ/dK 2 dt^2 rho c + dJ/dM 2 dt^2 c
       dJ/drho    = dJ/dK dt^2 c^2 - dJ/db / rho^2
-  each summed back from the layer onto the physical node it copies.  The paper
+  each summed back from the layer onto the physical node it copies.  The
+  source enters with M = K / rho, so the adjoint of the source map is
+  (F^T r)_s^n = sum_x (d_s / (dV rho)) phi^{n+1}.  The paper
   states no adjoint: this is the exact adjoint of the discrete forward map,
   pinned by finite differences of that map.
 """
@@ -420,11 +422,11 @@ def source_term(st, table, amplitudes):
     return q.reshape(st.prob.N)
 
 
-def gradient_vd(st, wavelet, src, rec, residual, history):
+def gradient_vd(st, wavelet, src, rec, residual, history, nsrc=0):
     """Velocity and density gradients of 1/2 sum (rec - d_obs)^2 for the
     staggered variable-density scheme, from the stored history u^0 .. u^N:
-    (dJ/dc, dJ/drho) on the physical grid and (dJ/dK, dJ/dM, dJ/db) on the
-    extended grid."""
+    (dJ/dc, dJ/drho) on the physical grid, (dJ/dK, dJ/dM, dJ/db) on the
+    extended grid and, when nsrc > 0, the adjoint of the source map F^T r."""
     prob = st.prob
     if prob.scheme != "vd_staggered":
         raise ValueError("gradient_vd covers the staggered variable-density scheme")
@@ -437,10 +439,14 @@ def gradient_vd(st, wavelet, src, rec, residual, history):
     gface = [np.zeros(tuple(N[a] + (2 * prob.r - 1 if a == i else 0) for a in range(prob.ndim)))
              for i in range(prob.ndim)]
     state = AdjointState(N)
+    src_adj = np.zeros((nsteps, nsrc)) if nsrc else None
     for m in range(nsteps, 0, -1):
         step(st, state.phi1, state.phi2)           # phi2 <- phi^m before injection
         phi = state.phi2
         inject(st, phi.reshape(-1), rec, residual[m - 1], divide_by_volume=False, weight=st.K)
+        if nsrc:
+            nodes, ids, w = src
+            src_adj[m - 1] = record(phi.reshape(-1), (nodes, ids, w * st.aux.ravel()[nodes] / prob.dV), nsrc)
         u = history[m - 1]                         # u^n with n = m - 1
         gK += phi * apply_L(st, u) / st.K
         if wavelet is not None:
@@ -453,7 +459,7 @@ def gradient_vd(st, wavelet, src, rec, residual, history):
     dt2 = prob.dt ** 2
     gc_ext = gK * 2.0 * dt2 * rho * st.c + gMsrc * 2.0 * dt2 * st.c
     grho_ext = gK * dt2 * st.c ** 2 - gb / rho ** 2
-    return (fold_to_physical(prob, gc_ext), fold_to_physical(prob, grho_ext), gK, gMsrc, gb)
+    return (fold_to_physical(prob, gc_ext), fold_to_physical(prob, grho_ext), gK, gMsrc, gb, src_adj)
 
 
 def gradient_checkpointed(st, wavelet, src, rec, nrec, residual_fn, every):

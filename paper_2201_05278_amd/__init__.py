@@ -6,6 +6,6 @@ condition) runs in libsimwave_hip.so, hand-written HIP for gfx950, behind the
 C ABI declared in include/simwave_hip.h.  This package is the thin Python
 binding over it.
 """
-from .propagator import (Propagator, ForwardResult, AcousticForward, Batch,  # noqa: F401
+from .propagator import (Propagator, ForwardResult, AcousticForward, AcousticForwardVD, Batch,  # noqa: F401
                          critical_dt, steps_for, ricker)
 from ._lib import SimwaveError, lib  # noqa: F401

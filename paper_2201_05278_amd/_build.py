@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsimwave_hip.so")
-SOURCES = ["plan.cpp", "api.cpp", "batch.cpp", "k_dispatch.cpp", "k_points.hip"] + \
+SOURCES = ["plan.cpp", "api.cpp", "batch.cpp", "k_dispatch.cpp", "k_points.hip", "k_adjoint_vd.hip"] + \
           [f"k_r{r}.hip" for r in range(1, 9)]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -62,7 +62,8 @@ class AdjIO(ctypes.Structure):
     _fields_ = [("workspace", c_void_p), ("vel", c_void_p), ("wavelet", c_void_p),
                 ("residual", c_void_p), ("ckpt", c_void_p), ("ckpt_every", c_int32),
                 ("field", c_void_p * 2), ("adj", c_void_p * 2), ("segment", c_void_p),
-                ("grad_m", c_void_p), ("grad_vel", c_void_p), ("src_adjoint", c_void_p)]
+                ("grad_m", c_void_p), ("grad_vel", c_void_p), ("src_adjoint", c_void_p),
+                ("grad_rho", c_void_p), ("vd_work", c_void_p)]
 
 
 class Tiling(ctypes.Structure):

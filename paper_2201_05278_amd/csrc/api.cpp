@@ -215,7 +215,7 @@ hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s)
     t.ts = 1;
     set_tiles(p, t, P);
     if (p->prob.scheme == SW_CONST) return launch_const(p->r, p->ndim, mode, t, P, s);
-    return launch_vd(p->prob.scheme, p->r, p->ndim, t, P, s);
+    return launch_vd(p->prob.scheme, mode, p->r, p->ndim, t, P, s);
 }
 
 bool two_step_ready(const sw_plan *p, const sw_fwd_io *io)
@@ -588,8 +588,13 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
     st = upload_points(p, p->rec, p->ws.rec, ws, s);
     if (st != SW_OK) return st;
     const float2 *damp = at<float2>(ws, p->ws.damp);
-    SW_HIP(launch_point_coef(table_dev(p, p->src, p->ws.src, ws), damp, vel, p->prob.dt, 1.0 / p->dV, s));
-    SW_HIP(launch_point_coef(table_dev(p, p->rec, p->ws.rec, ws), damp, vel, p->prob.dt, 1.0, s));
+    // staggered scheme: receivers inject the adjoint residual with the
+    // stencil's multiplier K, and the source adjoint is recorded with w / rho
+    const float *rho_stag = p->prob.scheme == SW_VD_STAGGERED ? rho : nullptr;
+    SW_HIP(launch_point_coef(table_dev(p, p->src, p->ws.src, ws), damp, vel, nullptr, rho_stag, p->prob.dt,
+                             1.0 / p->dV, s));
+    SW_HIP(launch_point_coef(table_dev(p, p->rec, p->ws.rec, ws), damp, vel, rho_stag, nullptr, p->prob.dt,
+                             1.0, s));
     p->prepared = true;
     p->prepared_ws = ws;
     return SW_OK;
@@ -755,8 +760,8 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
 {
     set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
-    if (p->prob.scheme != SW_CONST)
-        return fail(SW_ERR_UNSUPPORTED, "the adjoint covers the constant-density scheme");
+    if (p->prob.scheme == SW_VD_CENTRED)
+        return fail(SW_ERR_UNSUPPORTED, "the adjoint covers the constant-density and staggered schemes");
     if (p->mirror)
         return fail(SW_ERR_UNSUPPORTED, "the adjoint covers zero ghosts (no Dirichlet / Neumann sides)");
     sw_status st = check_prepared(p, io->workspace);
@@ -764,6 +769,9 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
     if (!io->residual || !io->ckpt || io->ckpt_every <= 0 || !io->field[0] || !io->field[1] ||
         !io->adj[0] || !io->adj[1] || !io->segment || !io->grad_m || !io->grad_vel || !io->vel)
         return fail(SW_ERR_ARG, "missing buffer");
+    const bool vd = p->prob.scheme == SW_VD_STAGGERED;
+    if (vd && (!io->grad_rho || !io->vd_work))
+        return fail(SW_ERR_ARG, "the staggered scheme needs grad_rho and vd_work");
     if (p->src.count && !io->wavelet) return fail(SW_ERR_ARG, "wavelet is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = io->workspace;
@@ -777,13 +785,24 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
     SW_HIP(launch_fill(io->grad_m, fe, 0.0f, s));
     SW_HIP(launch_fill(io->adj[0], fe, 0.0f, s));
     SW_HIP(launch_fill(io->adj[1], fe, 0.0f, s));
+    // staggered scheme: per-axis face sums (vd_work[0..2]) and the source term (vd_work[3])
+    float *face_sum[3] = {nullptr, nullptr, nullptr};
+    float *src_sum = nullptr;
+    const float *sj[3] = {P.sz, P.sx, P.sy};
+    if (vd) {
+        SW_HIP(launch_fill(io->vd_work, 4 * fe, 0.0f, s));
+        for (int a = 0; a < 3; ++a) face_sum[a] = io->vd_work + size_t(a) * fe;
+        src_sum = io->vd_work + size_t(3) * fe;
+    }
     float *acur = io->adj[0];   // phi^{m+1}
     float *anxt = io->adj[1];   // phi^{m+2}, overwritten by phi^m
     const int nseg = (N + E - 1) / E;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k = seg * E;
         const int L = std::min(E, N - k);
-        // restore (u^k, u^{k-1}) and recompute u^{k+1..k+L}, storing M (L u^n + Q s^n)
+        // restore (u^k, u^{k-1}) and recompute u^{k+1..k+L}, storing K L u^n plus,
+        // for constant density, the source part M Q s^n (the staggered scheme
+        // images the source separately and also keeps u^n for the face term)
         const float *slot = io->ckpt + size_t(seg) * 2 * fe;
         SW_HIP(launch_copy(io->field[0], slot, fe, s));
         SW_HIP(launch_copy(io->field[1], slot + fe, fe, s));
@@ -796,9 +815,12 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
             P.nxt = nxt;
             P.store = lvl;
             P.grad = nullptr;
+            P.ustore = vd ? io->segment + size_t(E + i) * fe : nullptr;
             SW_HIP(stencil(p, MODE_STORE, P, s));
-            if (src.count) SW_HIP(launch_inject(src, nxt, lvl, io->wavelet + size_t(n) * src.count, s));
+            if (src.count)
+                SW_HIP(launch_inject(src, nxt, vd ? nullptr : lvl, io->wavelet + size_t(n) * src.count, s));
         }
+        P.ustore = nullptr;
         // adjoint steps m = top .. k (top = N in the last segment)
         const int top = (seg == nseg - 1) ? N : k + L - 1;
         for (int m = top; m >= k; --m) {
@@ -808,6 +830,12 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
                 P.store = io->segment + size_t(m - k) * fe;
                 P.grad = io->grad_m;
                 SW_HIP(stencil(p, MODE_IMAGE, P, s));
+                if (vd) {   // phi^{m+1} (acur, left unchanged) against u^m
+                    SW_HIP(launch_face_image(make_geom(p), p->ndim, p->r, sj, acur,
+                                             io->segment + size_t(E + m - k) * fe, face_sum, s));
+                    if (src.count)
+                        SW_HIP(launch_src_image(src, acur, io->wavelet + size_t(m) * src.count, src_sum, s));
+                }
             } else {
                 P.store = nullptr;
                 P.grad = nullptr;
@@ -822,8 +850,20 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
         }
     }
     // the forward work buffers are free now and hold the fold's partial sums
-    SW_HIP(launch_fold_gradient(make_geom(p), io->grad_m, io->vel, p->prob.dt, io->grad_vel, io->field[0],
-                                io->field[1], s));
+    if (!vd) {
+        SW_HIP(launch_fold_gradient(make_geom(p), io->grad_m, io->vel, p->prob.dt, io->grad_vel, io->field[0],
+                                    io->field[1], s));
+        return SW_OK;
+    }
+    // staggered: x = (dJ/dK + S / K^2) / b -> dJ/dc = fold(x) 2 dt^2 c;
+    // y = dJ/dK K b - dJ/db b^2 -> dJ/drho = fold(y)
+    const Geom g = make_geom(p);
+    const float *Kf = at<float>(ws, p->ws.model_k);
+    const float *bf = at<float>(ws, p->ws.model_aux);
+    SW_HIP(launch_vd_chain(g, p->r, p->ndim, P.mj, io->grad_m, face_sum, src_sum, Kf, bf, io->field[0],
+                           io->field[1], s));
+    SW_HIP(launch_fold_gradient(g, io->field[0], io->vel, p->prob.dt, io->grad_vel, io->adj[0], io->adj[1], s));
+    SW_HIP(launch_fold(g, io->field[1], io->grad_rho, io->adj[0], io->adj[1], s));
     return SW_OK;
 }
 

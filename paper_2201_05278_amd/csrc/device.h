@@ -45,6 +45,7 @@ struct StencilParams {
     int ndamp;              // entries of damp
     float *store;           // MODE_STORE: K (L p) written; MODE_IMAGE: read
     float *grad;            // MODE_IMAGE: += p * store / K^2
+    float *ustore;          // MODE_STORE, staggered scheme: p^n written (the level imaged by the face term)
     Geom g;
     float c0;               // sum over axes of v_0 / h^2
     float cz[9], cx[9], cy[9];     // second-derivative v_j / h^2 per axis
@@ -122,7 +123,7 @@ struct TwoStepParams {
 
 hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s);
 hipError_t launch_const_two(int r, const Tiling &t, StencilParams &P, const TwoStepParams &T, hipStream_t s);
-hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
+hipError_t launch_vd(int scheme, int mode, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
 
 // ---- point and utility kernels ----
 struct PointTableDev {
@@ -173,8 +174,10 @@ hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int 
 // along each axis (b at the nearest grid node), at every padded position.
 hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, int r, const float *mj,
                                 const float *b, float *fz, float *fx, float *fy, hipStream_t s);
-hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel,
-                             double dt, double inv_dv, hipStream_t s);
+// rho_inj (or NULL) scales the injection multiplier to dt^2 rho c^2; rho_rec
+// (or NULL) divides the recording weights by rho (see k_point_coef).
+hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel, const float *rho_inj,
+                             const float *rho_rec, double dt, double inv_dv, hipStream_t s);
 hipError_t launch_inject(const PointTableDev &t, float *field, float *store, const float *amp,
                          hipStream_t s);
 // The values launch_inject would add, for two consecutive steps:
@@ -187,5 +190,19 @@ hipError_t launch_snapshot(const Geom &g, const float *field, float *out, hipStr
 // 2 dt^2 c; tmp0 / tmp1 hold Z*X*ny and Z*nx*ny floats.
 hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float *vel, double dt,
                                 float *grad_vel, float *tmp0, float *tmp1, hipStream_t s);
+// Fold an extended-grid field (padded layout) onto the physical grid, unscaled.
+hipError_t launch_fold(const Geom &g, const float *in, float *out, float *tmp0, float *tmp1, hipStream_t s);
+
+// ---- staggered variable-density imaging (k_adjoint_vd.hip) ----
+// F[axis] -= (D+ phi)(D+ u) on every face of each used axis; sj[axis][1..r] = s_j / h.
+hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, const float *phi,
+                             const float *u, float *const *F, hipStream_t s);
+// S += phi * (source part of the update) at the source nodes.
+hipError_t launch_src_image(const PointTableDev &t, const float *phi, const float *amp, float *S,
+                            hipStream_t s);
+// Per extended node: x = (gK + S / K^2) / b and y = gK K b - (dJ/db) b^2.
+hipError_t launch_vd_chain(const Geom &g, int r, int ndim, const float *mj, const float *gK,
+                           const float *const *F, const float *S, const float *K, const float *b,
+                           float *xout, float *yout, hipStream_t s);
 
 }  // namespace sw

@@ -5,28 +5,28 @@ namespace sw {
 
 hipError_t launch_const_r1(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r1(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r1(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r1(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r2(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r2(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r2(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r2(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r3(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r3(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r3(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r3(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r4(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r4(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r4(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r4(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r5(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r5(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r5(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r5(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r6(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r6(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r6(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r6(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r7(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r7(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r7(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r7(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_const_r8(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r8(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
-hipError_t launch_vd_r8(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_vd_r8(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 
 hipError_t launch_tb_r1(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
 hipError_t launch_tb_r2(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
@@ -83,17 +83,17 @@ hipError_t launch_const_two(int r, const Tiling &t, StencilParams &P, const TwoS
     }
 }
 
-hipError_t launch_vd(int scheme, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
+hipError_t launch_vd(int scheme, int mode, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
     switch (r) {
-    case 1: return launch_vd_r1(scheme, ndim, t, P, s);
-    case 2: return launch_vd_r2(scheme, ndim, t, P, s);
-    case 3: return launch_vd_r3(scheme, ndim, t, P, s);
-    case 4: return launch_vd_r4(scheme, ndim, t, P, s);
-    case 5: return launch_vd_r5(scheme, ndim, t, P, s);
-    case 6: return launch_vd_r6(scheme, ndim, t, P, s);
-    case 7: return launch_vd_r7(scheme, ndim, t, P, s);
-    case 8: return launch_vd_r8(scheme, ndim, t, P, s);
+    case 1: return launch_vd_r1(scheme, mode, ndim, t, P, s);
+    case 2: return launch_vd_r2(scheme, mode, ndim, t, P, s);
+    case 3: return launch_vd_r3(scheme, mode, ndim, t, P, s);
+    case 4: return launch_vd_r4(scheme, mode, ndim, t, P, s);
+    case 5: return launch_vd_r5(scheme, mode, ndim, t, P, s);
+    case 6: return launch_vd_r6(scheme, mode, ndim, t, P, s);
+    case 7: return launch_vd_r7(scheme, mode, ndim, t, P, s);
+    case 8: return launch_vd_r8(scheme, mode, ndim, t, P, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -132,21 +132,26 @@ __global__ void k_face_buoyancy(Geom g, int hz, int hx, int pz, int r, FaceCoef 
     }
 }
 
-// Per entry: A(node) dt^2 c(node)^2 w s (injection), dt^2 c^2 w s (the source
-// part of the stored M (L u + Q s) levels) and w s (recording), with s = 1/dV
-// for sources and 1 for receivers.
+// Per entry: A(node) W w s (injection), W w s (the source part of the stored
+// levels of the imaging condition) and w s / R (recording), with s = 1/dV for
+// sources and 1 for receivers.  W = dt^2 c^2, or dt^2 rho c^2 when rho_inj is
+// given (the receivers of a staggered variable-density plan, whose adjoint
+// spreads the residual with the stencil's multiplier K); R = 1, or rho when
+// rho_rec is given (the sources of such a plan: its adjoint level is K A mu,
+// and the source entered with M = K / rho).
 __global__ void k_point_coef(PointTableDev t, const float2 *__restrict__ damp,
-                             const float *__restrict__ vel, double dt, double scale)
+                             const float *__restrict__ vel, const float *__restrict__ rho_inj,
+                             const float *__restrict__ rho_rec, double dt, double scale)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= t.nent) return;
     const double c = vel[t.phys[e]];
-    const double m = dt * dt * c * c;
+    const double m = dt * dt * c * c * (rho_inj ? double(rho_inj[t.phys[e]]) : 1.0);
     const double a = damp[t.d2[e]].x;
     const double w = double(t.weight[e]) * scale;
     t.coef_a[e] = float(a * m * w);
     t.coef_s[e] = float(m * w);
-    t.wscaled[e] = float(w);
+    t.wscaled[e] = float(rho_rec ? w / double(rho_rec[t.phys[e]]) : w);
 }
 
 template <int G>
@@ -263,7 +268,8 @@ __global__ void k_snapshot(Geom g, const float *__restrict__ f, float *__restric
     }
 }
 
-// dJ/dc on the physical grid.  Every extended-grid node copies its model from
+// Fold onto the physical grid (dJ/dc when scaled by 2 dt^2 c, or unscaled when
+// vel is NULL).  Every extended-grid node copies its model from
 // the nearest physical node, so the transpose of that copy sums the layer
 // cells of each axis onto the physical edge cell.  The sum is separable and is
 // done one axis at a time (y, then x, then z), each pass summing at most
@@ -299,7 +305,7 @@ __global__ void k_fold_axis(Geom g, int pass, const float *__restrict__ in, floa
             else if (pass == 1) s += in[(int64_t(z) * ix + k) * iy + y];
             else s += in[(int64_t(k) * ix + x) * iy + y];
         }
-        out[i] = (pass == 2) ? s * two_dt2 * vel[i] : s;
+        out[i] = (pass == 2 && vel) ? s * two_dt2 * vel[i] : s;
     }
 }
 
@@ -378,12 +384,12 @@ hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, i
     return hipGetLastError();
 }
 
-hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel,
-                             double dt, double scale, hipStream_t s)
+hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel, const float *rho_inj,
+                             const float *rho_rec, double dt, double scale, hipStream_t s)
 {
     if (t.nent <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_point_coef, dim3(blocks_for(t.nent)), dim3(kBlock), 0, s, t, damp, vel,
-                       dt, scale);
+    hipLaunchKernelGGL(k_point_coef, dim3(blocks_for(t.nent)), dim3(kBlock), 0, s, t, damp, vel, rho_inj,
+                       rho_rec, dt, scale);
     return hipGetLastError();
 }
 
@@ -471,6 +477,11 @@ hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float 
     hipLaunchKernelGGL(k_fold_axis, dim3(blocks_for(n1)), dim3(kBlock), 0, s, g, 1, tmp0, tmp1, vel, two_dt2);
     hipLaunchKernelGGL(k_fold_axis, dim3(blocks_for(n2)), dim3(kBlock), 0, s, g, 2, tmp1, grad_vel, vel, two_dt2);
     return hipGetLastError();
+}
+
+hipError_t launch_fold(const Geom &g, const float *in, float *out, float *tmp0, float *tmp1, hipStream_t s)
+{
+    return launch_fold_gradient(g, in, nullptr, 0.0, out, tmp0, tmp1, s);
 }
 
 }  // namespace sw

@@ -21,9 +21,9 @@ hipError_t launch_tb_r8(const Tiling &t, StencilParams &P, const TwoStepParams &
     return launch_tb_radius<8>(t, P, T, s);
 }
 
-hipError_t launch_vd_r8(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
+hipError_t launch_vd_r8(int scheme, int mode, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    return launch_vd_radius<8>(scheme, ndim, t, P, s);
+    return launch_vd_radius<8>(scheme, mode, ndim, t, P, s);
 }
 
 }  // namespace sw

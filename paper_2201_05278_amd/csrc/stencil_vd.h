@@ -29,7 +29,7 @@ namespace sw {
 
 __device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-template <int R, int NDIM, int TX, int NW, int NT>
+template <int R, int NDIM, int TX, int NW, int NT, int MODE = MODE_FWD>
 __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
 {
     static_assert(TX % NW == 0, "rows must split evenly over waves");
@@ -91,6 +91,11 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     auto fsoff = [&](int z) -> int { return (z - fw) * pb; };
     const auto rk = buf_res(P.K + w0, wbytes);
     const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
+    // imaging arrays share the wavefield layout and window
+    __amdgpu_buffer_rsrc_t rs = rk, ru = rk, rg = rk;
+    if constexpr (MODE != MODE_FWD) rs = buf_res(P.store + w0, wbytes);
+    if constexpr (MODE == MODE_STORE) ru = buf_res(P.ustore + w0, wbytes);
+    if constexpr (MODE == MODE_IMAGE) rg = buf_res(P.grad + w0, wbytes);
     auto soff = [&](int z) -> int { return (z - zw) * pb; };
     auto zmask = [&](int z) -> unsigned {
         return axis_read(z, g.Z, P.bcm[0][0], P.bcm[0][1], P.gh) ? ~0u : 0u;
@@ -193,6 +198,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         float fp[RPT], fz[RPT], p[RPT], k[RPT];
         float2 ab[RPT];
         float hxp[HXN > 0 ? HXN : 1], hyp[YHN], ff[NIT];
+        float d[MODE == MODE_IMAGE ? RPT : 1], gr[MODE == MODE_IMAGE ? RPT : 1];
     };
     // loads of plane z: the queue input at z + 2R - 1 and the z-face buoyancy at
     // z + R - 1, and for z >= zb the plane's own p^{n-1}, K, (A, B), the halos
@@ -218,6 +224,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
             L.p[i] = buf_ld<NT>(rn, ro[i], so);
             L.k[i] = buf_ld<NT>(rk, ro[i], so);
             L.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
+            if constexpr (MODE == MODE_IMAGE) {
+                L.d[i] = buf_ld<NT>(rs, ro[i], so);
+                L.gr[i] = buf_ld<NT>(rg, ro[i], so);
+            }
         }
 #pragma unroll
         for (int s = 0; s < HXN; ++s) L.hxp[s] = buf_ld<0>(rc, hxo[s], so);
@@ -287,9 +297,16 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
                     dys = fmaf(P.sy[j], sfy[rr][lane + R + j - 1] - sfy[rr][lane + R - j], dys);
                 }
                 const float lap = dzs + dxs + dys;
-                float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, pq[i][u % Q], W.p[i]);
+                const float c = pq[i][u % Q];
+                float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, c, W.p[i]);
                 if (rdir[i] || axis_dirichlet(z, g.Z, P.bcm[0][0], P.bcm[0][1])) out = 0.0f;
                 buf_st<NT>(out, rn, ro[i], so);
+                if constexpr (MODE == MODE_STORE) {
+                    buf_st<NT>(W.k[i] * lap, rs, ro[i], so);
+                    buf_st<NT>(c, ru, ro[i], so);
+                }
+                if constexpr (MODE == MODE_IMAGE)
+                    buf_st<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.gr[i]), rg, ro[i], so);
             }
         }
     }
@@ -522,13 +539,22 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 // Tile shapes (rows, waves) of the variable-density kernels in 3D; 2D uses (1, 1).
 #define SW_VD_SHAPES(X) X(16, 8) X(8, 8) X(8, 4) X(16, 4)
 
+template <int R, int NDIM, int TX, int NW, int NT, int MODE>
+void launch_stag_mode(int occ, StencilParams &P, hipStream_t s)
+{
+    constexpr auto kern = k_stag<R, NDIM, TX, NW, NT, MODE>;
+    hipLaunchKernelGGL(kern, dim3(P.ntx * P.nty * P.nzc), dim3(64 * NW),
+                       occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u, s, P);
+}
+
 template <int R, int NDIM, int TX, int NW, int NT>
-hipError_t launch_vd_shape(int scheme, int occ, StencilParams &P, hipStream_t s)
+hipError_t launch_vd_shape(int scheme, int mode, int occ, StencilParams &P, hipStream_t s)
 {
     const dim3 grid(P.ntx * P.nty * P.nzc), block(64 * NW);
     if (scheme == 1) {
-        constexpr auto kern = k_stag<R, NDIM, TX, NW, NT>;
-        hipLaunchKernelGGL(kern, grid, block, occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u, s, P);
+        if (mode == MODE_STORE) launch_stag_mode<R, NDIM, TX, NW, NT, MODE_STORE>(occ, P, s);
+        else if (mode == MODE_IMAGE) launch_stag_mode<R, NDIM, TX, NW, NT, MODE_IMAGE>(occ, P, s);
+        else launch_stag_mode<R, NDIM, TX, NW, NT, MODE_FWD>(occ, P, s);
     } else {
         constexpr auto kern = k_cent<R, NDIM, TX, NW, NT>;
         hipLaunchKernelGGL(kern, grid, block, occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u, s, P);
@@ -537,20 +563,20 @@ hipError_t launch_vd_shape(int scheme, int occ, StencilParams &P, hipStream_t s)
 }
 
 template <int R, int NT>
-hipError_t launch_vd_nt(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
+hipError_t launch_vd_nt(int scheme, int mode, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    if (ndim == 2) return launch_vd_shape<R, 2, 1, 1, NT>(scheme, t.occ, P, s);
+    if (ndim == 2) return launch_vd_shape<R, 2, 1, 1, NT>(scheme, mode, t.occ, P, s);
 #define SW_X(TXV, NWV) \
-    if (t.tx == TXV && t.nw == NWV) return launch_vd_shape<R, 3, TXV, NWV, NT>(scheme, t.occ, P, s);
+    if (t.tx == TXV && t.nw == NWV) return launch_vd_shape<R, 3, TXV, NWV, NT>(scheme, mode, t.occ, P, s);
     SW_VD_SHAPES(SW_X)
 #undef SW_X
     return hipErrorInvalidValue;
 }
 
 template <int R>
-hipError_t launch_vd_radius(int scheme, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
+hipError_t launch_vd_radius(int scheme, int mode, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
-    return t.nt ? launch_vd_nt<R, 1>(scheme, ndim, t, P, s) : launch_vd_nt<R, 0>(scheme, ndim, t, P, s);
+    return t.nt ? launch_vd_nt<R, 1>(scheme, mode, ndim, t, P, s) : launch_vd_nt<R, 0>(scheme, mode, ndim, t, P, s);
 }
 
 }  // namespace sw

@@ -286,15 +286,20 @@ class Propagator:
 
     def adjoint(self, wavelet, residual, ckpt, checkpoint_every, want_src_adjoint=False):
         """Velocity gradient (physical grid) of 1/2 |traces - d_obs|^2 given the
-        residual dJ/dtraces and the forward checkpoints."""
+        residual dJ/dtraces and the forward checkpoints: (dJ/dc, F^T r or None,
+        dJ/dM on the extended grid).  Staggered variable-density plans return a
+        fourth element, dJ/drho on the physical grid."""
         lay = self.layout
         fe = lay.field_elems
         dev = self.device
+        vd = self.scheme == "vd_staggered"
         self._keep_adj = None          # the previous call's scratch can be reused
         work = [torch.empty(fe, dtype=torch.float32, device=dev) for _ in range(4)]
-        segment = torch.empty((checkpoint_every, fe), dtype=torch.float32, device=dev)
+        segment = torch.empty(((2 if vd else 1) * checkpoint_every, fe), dtype=torch.float32, device=dev)
         grad_m = torch.empty(fe, dtype=torch.float32, device=dev)
         grad_vel = torch.empty(self.n, dtype=torch.float32, device=dev)
+        grad_rho = torch.empty(self.n, dtype=torch.float32, device=dev) if vd else None
+        vd_work = torch.empty((4, fe), dtype=torch.float32, device=dev) if vd else None
         src_adj = None
         if want_src_adjoint and lay.nsrc:
             src_adj = torch.zeros((self.nsteps, lay.nsrc), dtype=torch.float32, device=dev)
@@ -314,8 +319,13 @@ class Propagator:
         io.grad_m = grad_m.data_ptr()
         io.grad_vel = grad_vel.data_ptr()
         io.src_adjoint = src_adj.data_ptr() if src_adj is not None else None
-        self._keep_adj = (work, segment, grad_m, residual, wavelet)
+        if vd:
+            io.grad_rho = grad_rho.data_ptr()
+            io.vd_work = vd_work.data_ptr()
+        self._keep_adj = (work, segment, grad_m, residual, wavelet, vd_work)
         L.check("sw_adjoint", L.lib().sw_adjoint(self._plan, ctypes.byref(io), _stream()))
+        if vd:
+            return grad_vel, src_adj, grad_m, grad_rho
         return grad_vel, src_adj, grad_m
 
 
@@ -397,3 +407,33 @@ class AcousticForward(torch.autograd.Function):
             prop.prepare(ctx.vel)      # the plan was re-prepared since this forward
         g, _, _ = prop.adjoint(ctx.wavelet, grad_traces, ctx.ckpt, ctx.every)
         return g, None, None, None
+
+
+class AcousticForwardVD(torch.autograd.Function):
+    """traces = F(vel, rho) for a staggered variable-density propagator;
+    backward gives (dJ/dvel, dJ/drho) by the hand-written adjoint with
+    checkpointed recomputation of the forward wavefield."""
+
+    @staticmethod
+    def forward(ctx, vel, rho, prop, wavelet, checkpoint_every):
+        if prop.scheme != "vd_staggered":
+            raise ValueError("AcousticForwardVD needs a staggered variable-density propagator")
+        vel = vel.detach().to(prop.device, torch.float32).contiguous()
+        rho = rho.detach().to(prop.device, torch.float32).contiguous()
+        prop.prepare(vel, rho)
+        res = prop.forward(wavelet, checkpoint_every=checkpoint_every)
+        ctx.prop = prop
+        ctx.vel, ctx.rho = vel, rho
+        ctx.wavelet = wavelet
+        ctx.ckpt = res.ckpt
+        ctx.every = checkpoint_every
+        return res.traces.clone()
+
+    @staticmethod
+    def backward(ctx, grad_traces):
+        prop = ctx.prop
+        if (prop._vel is None or prop._vel.data_ptr() != ctx.vel.data_ptr() or
+                prop._rho is None or prop._rho.data_ptr() != ctx.rho.data_ptr()):
+            prop.prepare(ctx.vel, ctx.rho)      # the plan was re-prepared since this forward
+        gv, _, _, gr = prop.adjoint(ctx.wavelet, grad_traces, ctx.ckpt, ctx.every)
+        return gv, gr, None, None, None

@@ -222,3 +222,15 @@ def test_occupancy_cap_and_default_tiles():
     vd = Propagator((40, 40, 40), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered", nbl=4)
     vd.set_tiling(8, 4, occ=5)
     assert vd.tiling["occ"] == 5
+
+
+def test_adjoint_scheme_contract():
+    # the centred variable-density operator is not symmetric: no adjoint for it;
+    # the staggered one is (it then needs a prepared plan like any other)
+    io = L.AdjIO()
+    cen = Propagator((20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_centred", nbl=2)
+    st = L.lib().sw_adjoint(cen._plan, ctypes.byref(io), None)
+    assert L.STATUS[st] == "SW_ERR_UNSUPPORTED"
+    stag = Propagator((20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered", nbl=2)
+    st = L.lib().sw_adjoint(stag._plan, ctypes.byref(io), None)
+    assert L.STATUS[st] == "SW_ERR_STATE"

@@ -214,3 +214,17 @@ def test_vd_gradients_match_finite_differences(n, nbl, so):
                   _vd_misfit(prob, *args_m, src, rec, nrec, wav, d_obs)) / (2 * eps)
             an = np.sum(g * d)
             assert abs(fd - an) < 2e-6 * max(abs(an), 1e-3 * np.abs(g).max()), (which, fd, an)
+
+
+@pytest.mark.parametrize("n", [(24, 28), (10, 11, 12)])
+def test_vd_dot_product(n):
+    # <F s, r> = <s, F^T r> for the staggered scheme's source-to-trace map
+    prob, c, rho, src, rec, nrec, wav, rng = _vd_setup(n=n, nbl=4, so=4, nt=50)
+    st = oracle.prepare(prob, c, rho)
+    nsrc = wav.shape[1]
+    s = rng.standard_normal((prob.nsteps, nsrc))
+    r = rng.standard_normal((prob.nsteps, nrec))
+    fw = oracle.forward(st, s, src, rec, nrec, keep_history=True)
+    FTr = oracle.gradient_vd(st, s, src, rec, r, fw.history, nsrc=nsrc)[5]
+    lhs, rhs = np.sum(fw.traces * r), np.sum(s * FTr)
+    assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), abs(rhs))
