@@ -83,10 +83,10 @@ def time_fwd_adjoint(prop, wavelet, every):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fw = prop.forward(wavelet, checkpoint_every=every)
-    g, _, _ = prop.adjoint(wavelet, fw.traces, fw.ckpt, every)
+    grads = prop.adjoint(wavelet, fw.traces, fw.ckpt, every)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    del fw, g
+    del fw, grads
     return el
 
 
@@ -308,6 +308,15 @@ def main():
         log(f"bench: vd staggered {vd:.1f} Gpts/s")
         del propv
         torch.cuda.empty_cache()
+        # forward + adjoint with velocity and density gradients
+        log("bench: variable-density forward + adjoint")
+        propva = make_prop(wl, "vd_staggered", KA, dt)
+        time_fwd_adjoint(propva, wava, args.ckpt_every)      # warm-up pass
+        el_va = time_fwd_adjoint(propva, wava, args.ckpt_every)
+        out["vd_fwd_adjoint_gpts"] = round(nodes * KA / el_va / 1e9, 3)
+        log(f"bench: vd fwd+adjoint {out['vd_fwd_adjoint_gpts']:.1f} Gpts/s")
+        del propva
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.skip_cpu:
@@ -335,6 +344,7 @@ def main():
         "fwd_adjoint_config": f"{KA} steps, checkpoints every {args.ckpt_every}, Gpts/s per "
                               f"original step (forward + recompute + adjoint with imaging)",
         "vd_staggered_gpts": None if vd is None else round(vd, 3),
+        "vd_fwd_adjoint_gpts": out.get("vd_fwd_adjoint_gpts"),
         "pct_hbm_peak_forward": round(100.0 * gpts * BYTES_PER_NODE["const"] / HBM_PEAK_GBS, 2),
         "pct_hbm_peak_fwd_adjoint": round(100.0 * fa * 64 / HBM_PEAK_GBS, 2),
         "pct_hbm_peak_vd": None if vd is None else round(100.0 * vd * 20 / HBM_PEAK_GBS, 2),

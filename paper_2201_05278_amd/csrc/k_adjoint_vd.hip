@@ -38,15 +38,16 @@ int grid_blocks(int64_t n)
     return int(b);
 }
 
-// One thread per face of `axis`: the face box is m = -r .. n + r - 2 along the
-// axis and the grid along the other two; the face sum of face m lives at the
-// padded position of node m (inside the stored halo for m < 0 or m >= n).
-__global__ void k_face_image(Geom g, int axis, int r, AxisCoef c, const float *__restrict__ phi,
-                             const float *__restrict__ u, float *__restrict__ F)
+// Faces outside the grid's node range, one thread each: m = -r .. -1 and
+// m = n .. n + r - 2 along `axis` (the 2r - 1 faces that no grid node owns),
+// the grid along the other two axes.  The face sum of face m lives at the
+// padded position of node m, inside the stored halo.
+__global__ void k_face_image_outer(Geom g, int axis, int r, AxisCoef c, const float *__restrict__ phi,
+                                   const float *__restrict__ u, float *__restrict__ F)
 {
     const int n[3] = {g.Z, g.X, g.Y};
     int e[3] = {n[0], n[1], n[2]};
-    e[axis] = n[axis] + 2 * r - 1;
+    e[axis] = 2 * r - 1;
     const int64_t total = int64_t(e[0]) * e[1] * e[2];
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * blockDim.x) {
@@ -55,7 +56,7 @@ __global__ void k_face_image(Geom g, int axis, int r, AxisCoef c, const float *_
         const int64_t t = i / e[2];
         k[1] = int(t % e[1]);
         k[0] = int(t / e[1]);
-        k[axis] -= r;                                   // face index m
+        k[axis] = (k[axis] < r) ? k[axis] - r : n[axis] + k[axis] - r;   // face index m
         const int m = k[axis];
         auto at = [&](const float *f, int v) -> float {  // node v along the axis, zero off the grid
             if (v < 0 || v >= n[axis]) return 0.0f;
@@ -71,6 +72,131 @@ __global__ void k_face_image(Geom g, int axis, int r, AxisCoef c, const float *_
         const int64_t o = elem(g, k[0], k[1], k[2]);
         F[o] = fmaf(-dp, du, F[o]);
     }
+}
+
+struct FaceTileParams {
+    Geom g;
+    float sz[9], sx[9], sy[9];      // s_j / h per axis
+    const float *phi, *u;
+    float *F[3];
+    int ntx, nty, nzc, zc;
+};
+
+// The faces k + 1/2 of every grid node k along each axis, one tile of
+// TX = NW * RPT rows x 64 columns per block marching along a z chunk (each
+// thread owns RPT rows of one column).  z differences come from rotating
+// register queues of phi and u (2R planes, compile-time slots), x and y
+// differences from the plane staged in LDS with R - 1 nodes of halo below and
+// R above: the tile's own nodes from the queues, the halo from memory; off-grid
+// nodes read zero.
+template <int R, int NDIM, int NW, int RPT>
+__global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
+{
+    constexpr int TX = NW * RPT;
+    constexpr int HL = R - 1;
+    constexpr int LXR = (NDIM == 3) ? TX + 2 * R - 1 : 1;
+    constexpr int LYC = 64 + 2 * R - 1;
+    constexpr int Q = 2 * R;
+    constexpr int NTH = 64 * NW;
+    constexpr int R0 = (NDIM == 3) ? HL : 0;     // LDS row of the tile's first row (2D: one row, no x halo)
+    static_assert(NDIM == 3 || (NW == 1 && RPT == 1), "2D tiles are one row");
+    __shared__ float sp[LXR][LYC], su[LXR][LYC];
+    const Geom &g = P.g;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int ty = bid % P.nty;
+    const int rest = bid / P.nty;
+    const int tx = rest % P.ntx;
+    const int zc = rest / P.ntx;
+    const int y0 = ty * 64, x0 = tx * TX;
+    const int y = y0 + lane;
+    const int zb = zc * P.zc;
+    const int ze = min(zb + P.zc, g.Z);
+    auto val = [&](const float *f, int z, int xx, int yy) -> float {
+        return (z >= 0 && z < g.Z && xx >= 0 && xx < g.X && yy >= 0 && yy < g.Y) ? f[elem(g, z, xx, yy)]
+                                                                              : 0.0f;
+    };
+    // slot (s + k) % Q of row i holds the value at z - R + 1 + k on step s (z = zz + s)
+    float qp[RPT][Q], qu[RPT][Q];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int x = x0 + wave * RPT + i;
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k) {
+            qp[i][k] = val(P.phi, zb - R + 1 + k, x, y);
+            qu[i][k] = val(P.u, zb - R + 1 + k, x, y);
+        }
+    }
+    for (int zz = zb; zz < ze; zz += Q) {
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const int z = zz + s;
+            if (z >= ze) break;
+            // this plane's face sums are loaded first, so that they arrive
+            // while the plane is staged
+            float f0[RPT], f1[RPT], f2[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int x = x0 + wave * RPT + i;
+                const bool own = x < g.X && y < g.Y;
+                const int64_t o = own ? elem(g, z, x, y) : 0;
+                f0[i] = own ? P.F[0][o] : 0.0f;
+                f1[i] = (NDIM == 3 && own) ? P.F[1][o] : 0.0f;
+                f2[i] = own ? P.F[2][o] : 0.0f;
+                qp[i][(s + Q - 1) % Q] = val(P.phi, z + R, x, y);
+                qu[i][(s + Q - 1) % Q] = val(P.u, z + R, x, y);
+                sp[R0 + wave * RPT + i][HL + lane] = qp[i][(s + R - 1) % Q];
+                su[R0 + wave * RPT + i][HL + lane] = qu[i][(s + R - 1) % Q];
+            }
+            for (int e = threadIdx.x; e < LXR * LYC; e += NTH) {
+                const int i = e / LYC, j = e % LYC;
+                if (i >= R0 && i < R0 + TX && j >= HL && j < HL + 64) continue;   // the tile's own nodes
+                const int xx = (NDIM == 3) ? x0 - HL + i : 0;
+                const int yy = y0 - HL + j;
+                sp[i][j] = val(P.phi, z, xx, yy);
+                su[i][j] = val(P.u, z, xx, yy);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int x = x0 + wave * RPT + i;
+                float dpz = 0.0f, duz = 0.0f, dpx = 0.0f, dux = 0.0f, dpy = 0.0f, duy = 0.0f;
+                const int ci = R0 + wave * RPT + i, cj = HL + lane;
+#pragma unroll
+                for (int l = 1; l <= R; ++l) {
+                    dpz = fmaf(P.sz[l], qp[i][(s + R - 1 + l) % Q] - qp[i][(s + R - l) % Q], dpz);
+                    duz = fmaf(P.sz[l], qu[i][(s + R - 1 + l) % Q] - qu[i][(s + R - l) % Q], duz);
+                    if constexpr (NDIM == 3) {
+                        dpx = fmaf(P.sx[l], sp[ci + l][cj] - sp[ci - l + 1][cj], dpx);
+                        dux = fmaf(P.sx[l], su[ci + l][cj] - su[ci - l + 1][cj], dux);
+                    }
+                    dpy = fmaf(P.sy[l], sp[ci][cj + l] - sp[ci][cj - l + 1], dpy);
+                    duy = fmaf(P.sy[l], su[ci][cj + l] - su[ci][cj - l + 1], duy);
+                }
+                if (x < g.X && y < g.Y) {
+                    const int64_t o = elem(g, z, x, y);
+                    P.F[0][o] = fmaf(-dpz, duz, f0[i]);
+                    if constexpr (NDIM == 3) P.F[1][o] = fmaf(-dpx, dux, f1[i]);
+                    P.F[2][o] = fmaf(-dpy, duy, f2[i]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// 3D tiles of 4 waves with 2 rows each up to radius 4, 1 row beyond (the
+// queues of longer stencils take the registers); 2D tiles of one row.
+constexpr int face_rows_per_thread(int r) { return r <= 4 ? 2 : 1; }
+
+template <int R>
+void launch_face_tile(int ndim, FaceTileParams &P, hipStream_t s)
+{
+    if (ndim == 2)
+        hipLaunchKernelGGL((k_face_tile<R, 2, 1, 1>), dim3(P.ntx * P.nty * P.nzc), dim3(64), 0, s, P);
+    else
+        hipLaunchKernelGGL((k_face_tile<R, 3, 4, face_rows_per_thread(R)>), dim3(P.ntx * P.nty * P.nzc),
+                           dim3(256), 0, s, P);
 }
 
 // One thread per unique source node: S(x) += phi(x) sum_e coef_s[e] amp[pid[e]]
@@ -150,16 +276,44 @@ __global__ void k_vd_chain(Geom g, int r, int ndim, MidCoef c, const float *__re
 hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, const float *phi,
                              const float *u, float *const *F, hipStream_t s)
 {
+    if (r < 1 || r > 8) return hipErrorInvalidValue;
+    // faces of the grid nodes: z-marching tiles
+    FaceTileParams T{};
+    T.g = g;
+    for (int l = 1; l <= r; ++l) {
+        T.sz[l] = sj[0][l];
+        T.sx[l] = sj[1][l];
+        T.sy[l] = sj[2][l];
+    }
+    T.phi = phi;
+    T.u = u;
+    for (int a = 0; a < 3; ++a) T.F[a] = F[a];
+    const int tx = (ndim == 2) ? 1 : 4 * face_rows_per_thread(r);
+    T.ntx = (g.X + tx - 1) / tx;
+    T.nty = (g.Y + 63) / 64;
+    T.zc = (ndim == 2) ? 16 : 32;
+    T.nzc = (g.Z + T.zc - 1) / T.zc;
+    switch (r) {
+    case 1: launch_face_tile<1>(ndim, T, s); break;
+    case 2: launch_face_tile<2>(ndim, T, s); break;
+    case 3: launch_face_tile<3>(ndim, T, s); break;
+    case 4: launch_face_tile<4>(ndim, T, s); break;
+    case 5: launch_face_tile<5>(ndim, T, s); break;
+    case 6: launch_face_tile<6>(ndim, T, s); break;
+    case 7: launch_face_tile<7>(ndim, T, s); break;
+    default: launch_face_tile<8>(ndim, T, s); break;
+    }
+    // faces no grid node owns (m < 0 or m >= n along each axis)
     const int n[3] = {g.Z, g.X, g.Y};
     for (int axis = 0; axis < 3; ++axis) {
         if (ndim == 2 && axis == 1) continue;
         AxisCoef c{};
         for (int l = 1; l <= r; ++l) c.s[l] = sj[axis][l];
         int e[3] = {n[0], n[1], n[2]};
-        e[axis] += 2 * r - 1;
+        e[axis] = 2 * r - 1;
         const int64_t total = int64_t(e[0]) * e[1] * e[2];
-        hipLaunchKernelGGL(k_face_image, dim3(grid_blocks(total)), dim3(kBlock), 0, s, g, axis, r, c, phi, u,
-                           F[axis]);
+        hipLaunchKernelGGL(k_face_image_outer, dim3(grid_blocks(total)), dim3(kBlock), 0, s, g, axis, r, c, phi,
+                           u, F[axis]);
     }
     return hipGetLastError();
 }

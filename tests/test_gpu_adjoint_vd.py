@@ -72,6 +72,7 @@ def _rel(a, b):
     ((40, 37), 16, 60, 5, 7),      # 2D, the highest order
     ((26, 31, 70), 4, 50, 4, 13),  # 3D: several tiles along x and y, ragged
     ((26, 31, 70), 8, 50, 4, 50),
+    ((22, 37, 70), 12, 40, 3, 9),  # 3D, long stencil (two rows per thread in the face pass)
 ])
 def test_vd_gradients_match_oracle(n, so, nsteps, nbl, every):
     args = _case(n, so, nsteps, nbl)
