@@ -105,3 +105,72 @@ def test_smooth_512_centred(smooth512):
 
 def test_layered_256_so16():
     _one_step_parity(workloads.layered_3d(n=256, nsteps=8), "const")
+
+
+def _fullsize_prop(wl, scheme, nsteps):
+    dt = workloads.CFL_FRACTION * oracle.coeffs.critical_dt(wl.h, wl.space_order, wl.cmax)
+    prop = Propagator(wl.n, wl.h, wl.space_order, dt, nsteps, scheme=scheme, nbl=wl.nbl)
+    prop.set_sources(wl.src, wl.src_interp)
+    prop.set_receivers(wl.rec, wl.rec_interp)
+    return prop, dt
+
+
+@pytest.mark.parametrize("scheme", ["const", "vd_staggered"])
+def test_smooth_512_adjoint_dot_product(smooth512, scheme):
+    # <F s, r> = <s, F^T r> at the benchmark size, default tiling, partial
+    # checkpoint segment: a property of the adjoint that holds at any size
+    wl = smooth512
+    nsteps, every = 30, 12
+    prop, dt = _fullsize_prop(wl, scheme, nsteps)
+    rho = None if scheme == "const" else torch.from_numpy(wl.rho).cuda()
+    prop.prepare(torch.from_numpy(wl.vel).cuda(), rho, cmax=wl.cmax)
+    print(f"case: full-size adjoint dot product, {scheme}", flush=True)
+    rng = np.random.default_rng(5)
+    s = torch.from_numpy(rng.standard_normal((nsteps, 1)).astype(np.float32)).cuda()
+    r = torch.from_numpy(rng.standard_normal((nsteps, len(wl.rec))).astype(np.float32)).cuda()
+    fw = prop.forward(s, checkpoint_every=every)
+    out = prop.adjoint(s, r, fw.ckpt, every, want_src_adjoint=True)
+    torch.cuda.synchronize()
+    lhs = float((fw.traces.double() * r.double()).sum())
+    rhs = float((s.double() * out[1].double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+
+
+def test_smooth_512_vd_gradients_match_finite_differences(smooth512):
+    # directional derivatives of the FP32 misfit against the velocity and the
+    # density gradients at the benchmark size (smooth directions)
+    wl = smooth512
+    nsteps, every = 40, 16
+    prop, dt = _fullsize_prop(wl, "vd_staggered", nsteps)
+    vel = torch.from_numpy(wl.vel).cuda()
+    rho = torch.from_numpy(wl.rho).cuda()
+    wav = torch.from_numpy(oracle.ricker(25.0, dt, nsteps, t0=12 * dt)[:, None].astype(np.float32)).cuda()
+    n = wl.n
+    axes = [torch.sin(torch.pi * (torch.arange(k, device="cuda", dtype=torch.float32) + 0.5) / k) for k in n]
+    bump = axes[0][:, None, None] * axes[1][None, :, None] * axes[2][None, None, :]
+
+    def traces(v, r_):
+        prop.prepare(v, r_, cmax=wl.cmax * 1.05)
+        t = prop.forward(wav).traces.clone()
+        torch.cuda.synchronize()
+        return t
+
+    print("case: full-size VD gradients vs finite differences", flush=True)
+    d_obs = traces(vel * (1.0 + 0.03 * bump), rho * (1.0 - 0.05 * bump))
+    prop.prepare(vel, rho, cmax=wl.cmax * 1.05)
+    fw = prop.forward(wav, checkpoint_every=every)
+    gv, _, _, gr = prop.adjoint(wav, fw.traces - d_obs, fw.ckpt, every)
+    torch.cuda.synchronize()
+
+    def misfit(v, r_):
+        return 0.5 * float(((traces(v, r_).double() - d_obs.double()) ** 2).sum())
+
+    for name, g, base in (("vel", gv, vel), ("rho", gr, rho)):
+        eps = 2e-3 * float(base.mean())
+        d = bump
+        if name == "vel":
+            fd = (misfit(vel + eps * d, rho) - misfit(vel - eps * d, rho)) / (2 * eps)
+        else:
+            fd = (misfit(vel, rho + eps * d) - misfit(vel, rho - eps * d)) / (2 * eps)
+        an = float((g.double() * d.double()).sum())
+        assert abs(fd - an) <= 2e-2 * abs(an), (name, fd, an)
