@@ -797,6 +797,12 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
     float *acur = io->adj[0];   // phi^{m+1}
     float *anxt = io->adj[1];   // phi^{m+2}, overwritten by phi^m
     const int nseg = (N + E - 1) / E;
+    const Geom gm = make_geom(p);
+    // staggered face term, formed two steps at a time: the term of step m
+    // (phi^{m+1} against u^m) is deferred to the start of step m - 1, where
+    // phi^{m+1} is still held (anxt) next to phi^m (acur); a step left over at
+    // the end of a segment is formed alone
+    auto u_level = [&](int m, int k) -> const float * { return io->segment + size_t(E + m - k) * fe; };
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k = seg * E;
         const int L = std::min(E, N - k);
@@ -823,19 +829,26 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
         P.ustore = nullptr;
         // adjoint steps m = top .. k (top = N in the last segment)
         const int top = (seg == nseg - 1) ? N : k + L - 1;
+        int pend = -1;              // imaging step whose face term is deferred
         for (int m = top; m >= k; --m) {
             P.cur = acur;
             P.nxt = anxt;
             if (m <= N - 1) {
+                if (vd) {
+                    if (pend == m + 1) {   // (phi^{m+2}, u^{m+1}) then (phi^{m+1}, u^m), before anxt is overwritten
+                        const float *ph[2] = {anxt, acur};
+                        const float *uu[2] = {u_level(m + 1, k), u_level(m, k)};
+                        SW_HIP(launch_face_image(gm, p->ndim, p->r, sj, 2, ph, uu, face_sum, s));
+                        pend = -1;
+                    } else {
+                        pend = m;
+                    }
+                    if (src.count)   // phi^{m+1} (acur, left unchanged by the step) at the sources
+                        SW_HIP(launch_src_image(src, acur, io->wavelet + size_t(m) * src.count, src_sum, s));
+                }
                 P.store = io->segment + size_t(m - k) * fe;
                 P.grad = io->grad_m;
                 SW_HIP(stencil(p, MODE_IMAGE, P, s));
-                if (vd) {   // phi^{m+1} (acur, left unchanged) against u^m
-                    SW_HIP(launch_face_image(make_geom(p), p->ndim, p->r, sj, acur,
-                                             io->segment + size_t(E + m - k) * fe, face_sum, s));
-                    if (src.count)
-                        SW_HIP(launch_src_image(src, acur, io->wavelet + size_t(m) * src.count, src_sum, s));
-                }
             } else {
                 P.store = nullptr;
                 P.grad = nullptr;
@@ -847,6 +860,11 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
                     SW_HIP(launch_record(src, anxt, io->src_adjoint + size_t(m - 1) * src.count, s));
             }
             std::swap(acur, anxt);   // phi^m becomes the current level
+        }
+        if (pend >= 0) {   // step k alone: phi^{k+1} is now anxt
+            const float *ph[1] = {anxt};
+            const float *uu[1] = {u_level(pend, k)};
+            SW_HIP(launch_face_image(gm, p->ndim, p->r, sj, 1, ph, uu, face_sum, s));
         }
     }
     // the forward work buffers are free now and hold the fold's partial sums

@@ -194,9 +194,10 @@ hipError_t launch_fold_gradient(const Geom &g, const float *grad_m, const float 
 hipError_t launch_fold(const Geom &g, const float *in, float *out, float *tmp0, float *tmp1, hipStream_t s);
 
 // ---- staggered variable-density imaging (k_adjoint_vd.hip) ----
-// F[axis] -= (D+ phi)(D+ u) on every face of each used axis; sj[axis][1..r] = s_j / h.
-hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, const float *phi,
-                             const float *u, float *const *F, hipStream_t s);
+// F[axis] -= (D+ phi[k])(D+ u[k]) on every face of each used axis, for the np
+// (1 or 2) level pairs k in order; sj[axis][1..r] = s_j / h.
+hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, int np,
+                             const float *const *phi, const float *const *u, float *const *F, hipStream_t s);
 // S += phi * (source part of the update) at the source nodes.
 hipError_t launch_src_image(const PointTableDev &t, const float *phi, const float *amp, float *S,
                             hipStream_t s);

@@ -77,19 +77,20 @@ __global__ void k_face_image_outer(Geom g, int axis, int r, AxisCoef c, const fl
 struct FaceTileParams {
     Geom g;
     float sz[9], sx[9], sy[9];      // s_j / h per axis
-    const float *phi, *u;
+    const float *phi[2], *u[2];     // level pairs, accumulated in this order
     float *F[3];
     int ntx, nty, nzc, zc;
 };
 
-// The faces k + 1/2 of every grid node k along each axis, one tile of
-// TX = NW * RPT rows x 64 columns per block marching along a z chunk (each
-// thread owns RPT rows of one column).  z differences come from rotating
-// register queues of phi and u (2R planes, compile-time slots), x and y
+// The faces k + 1/2 of every grid node k along each axis for NP level pairs
+// (phi, u) at once, one tile of TX = NW * RPT rows x 64 columns per block
+// marching along a z chunk (each thread owns RPT rows of one column): the face
+// sums are read and written once for all pairs.  z differences come from
+// rotating register queues (2R planes, compile-time slots), x and y
 // differences from the plane staged in LDS with R - 1 nodes of halo below and
 // R above: the tile's own nodes from the queues, the halo from memory; off-grid
 // nodes read zero.
-template <int R, int NDIM, int NW, int RPT>
+template <int R, int NDIM, int NW, int RPT, int NP>
 __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
 {
     constexpr int TX = NW * RPT;
@@ -98,10 +99,14 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
     constexpr int LYC = 64 + 2 * R - 1;
     constexpr int Q = 2 * R;
     constexpr int NTH = 64 * NW;
+    constexpr int NF = 2 * NP;                   // staged fields: phi and u of each pair
     constexpr int R0 = (NDIM == 3) ? HL : 0;     // LDS row of the tile's first row (2D: one row, no x halo)
     static_assert(NDIM == 3 || (NW == 1 && RPT == 1), "2D tiles are one row");
-    __shared__ float sp[LXR][LYC], su[LXR][LYC];
+    __shared__ float sf[NF][LXR][LYC];
     const Geom &g = P.g;
+    const float *src[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) src[f] = (f & 1) ? P.u[f >> 1] : P.phi[f >> 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ty = bid % P.nty;
@@ -116,17 +121,14 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
         return (z >= 0 && z < g.Z && xx >= 0 && xx < g.X && yy >= 0 && yy < g.Y) ? f[elem(g, z, xx, yy)]
                                                                               : 0.0f;
     };
-    // slot (s + k) % Q of row i holds the value at z - R + 1 + k on step s (z = zz + s)
-    float qp[RPT][Q], qu[RPT][Q];
+    // slot (s + k) % Q of field f, row i holds the value at z - R + 1 + k on step s (z = zz + s)
+    float q[NF][RPT][Q];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int x = x0 + wave * RPT + i;
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) {
-            qp[i][k] = val(P.phi, zb - R + 1 + k, x, y);
-            qu[i][k] = val(P.u, zb - R + 1 + k, x, y);
-        }
-    }
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int k = 0; k < Q - 1; ++k) q[f][i][k] = val(src[f], zb - R + 1 + k, x0 + wave * RPT + i, y);
     for (int zz = zb; zz < ze; zz += Q) {
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
@@ -143,41 +145,50 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
                 f0[i] = own ? P.F[0][o] : 0.0f;
                 f1[i] = (NDIM == 3 && own) ? P.F[1][o] : 0.0f;
                 f2[i] = own ? P.F[2][o] : 0.0f;
-                qp[i][(s + Q - 1) % Q] = val(P.phi, z + R, x, y);
-                qu[i][(s + Q - 1) % Q] = val(P.u, z + R, x, y);
-                sp[R0 + wave * RPT + i][HL + lane] = qp[i][(s + R - 1) % Q];
-                su[R0 + wave * RPT + i][HL + lane] = qu[i][(s + R - 1) % Q];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    q[f][i][(s + Q - 1) % Q] = val(src[f], z + R, x, y);
+                    sf[f][R0 + wave * RPT + i][HL + lane] = q[f][i][(s + R - 1) % Q];
+                }
             }
             for (int e = threadIdx.x; e < LXR * LYC; e += NTH) {
                 const int i = e / LYC, j = e % LYC;
                 if (i >= R0 && i < R0 + TX && j >= HL && j < HL + 64) continue;   // the tile's own nodes
                 const int xx = (NDIM == 3) ? x0 - HL + i : 0;
                 const int yy = y0 - HL + j;
-                sp[i][j] = val(P.phi, z, xx, yy);
-                su[i][j] = val(P.u, z, xx, yy);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) sf[f][i][j] = val(src[f], z, xx, yy);
             }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int x = x0 + wave * RPT + i;
-                float dpz = 0.0f, duz = 0.0f, dpx = 0.0f, dux = 0.0f, dpy = 0.0f, duy = 0.0f;
                 const int ci = R0 + wave * RPT + i, cj = HL + lane;
+                float a0 = f0[i], a1 = f1[i], a2 = f2[i];
 #pragma unroll
-                for (int l = 1; l <= R; ++l) {
-                    dpz = fmaf(P.sz[l], qp[i][(s + R - 1 + l) % Q] - qp[i][(s + R - l) % Q], dpz);
-                    duz = fmaf(P.sz[l], qu[i][(s + R - 1 + l) % Q] - qu[i][(s + R - l) % Q], duz);
-                    if constexpr (NDIM == 3) {
-                        dpx = fmaf(P.sx[l], sp[ci + l][cj] - sp[ci - l + 1][cj], dpx);
-                        dux = fmaf(P.sx[l], su[ci + l][cj] - su[ci - l + 1][cj], dux);
+                for (int pr = 0; pr < NP; ++pr) {
+                    const int fp = 2 * pr, fu = 2 * pr + 1;
+                    float dpz = 0.0f, duz = 0.0f, dpx = 0.0f, dux = 0.0f, dpy = 0.0f, duy = 0.0f;
+#pragma unroll
+                    for (int l = 1; l <= R; ++l) {
+                        dpz = fmaf(P.sz[l], q[fp][i][(s + R - 1 + l) % Q] - q[fp][i][(s + R - l) % Q], dpz);
+                        duz = fmaf(P.sz[l], q[fu][i][(s + R - 1 + l) % Q] - q[fu][i][(s + R - l) % Q], duz);
+                        if constexpr (NDIM == 3) {
+                            dpx = fmaf(P.sx[l], sf[fp][ci + l][cj] - sf[fp][ci - l + 1][cj], dpx);
+                            dux = fmaf(P.sx[l], sf[fu][ci + l][cj] - sf[fu][ci - l + 1][cj], dux);
+                        }
+                        dpy = fmaf(P.sy[l], sf[fp][ci][cj + l] - sf[fp][ci][cj - l + 1], dpy);
+                        duy = fmaf(P.sy[l], sf[fu][ci][cj + l] - sf[fu][ci][cj - l + 1], duy);
                     }
-                    dpy = fmaf(P.sy[l], sp[ci][cj + l] - sp[ci][cj - l + 1], dpy);
-                    duy = fmaf(P.sy[l], su[ci][cj + l] - su[ci][cj - l + 1], duy);
+                    a0 = fmaf(-dpz, duz, a0);
+                    if constexpr (NDIM == 3) a1 = fmaf(-dpx, dux, a1);
+                    a2 = fmaf(-dpy, duy, a2);
                 }
                 if (x < g.X && y < g.Y) {
                     const int64_t o = elem(g, z, x, y);
-                    P.F[0][o] = fmaf(-dpz, duz, f0[i]);
-                    if constexpr (NDIM == 3) P.F[1][o] = fmaf(-dpx, dux, f1[i]);
-                    P.F[2][o] = fmaf(-dpy, duy, f2[i]);
+                    P.F[0][o] = a0;
+                    if constexpr (NDIM == 3) P.F[1][o] = a1;
+                    P.F[2][o] = a2;
                 }
             }
             __syncthreads();
@@ -185,18 +196,25 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
     }
 }
 
-// 3D tiles of 4 waves with 2 rows each up to radius 4, 1 row beyond (the
-// queues of longer stencils take the registers); 2D tiles of one row.
-constexpr int face_rows_per_thread(int r) { return r <= 4 ? 2 : 1; }
+// 3D tiles of 4 waves with 2 rows each for one pair up to radius 4, 1 row
+// otherwise (the queues take the registers); 2D tiles of one row.
+constexpr int face_rows_per_thread(int r, int np) { return (r <= 4 && np == 1) ? 2 : 1; }
 
-template <int R>
-void launch_face_tile(int ndim, FaceTileParams &P, hipStream_t s)
+template <int R, int NP>
+void launch_face_tile_np(int ndim, FaceTileParams &P, hipStream_t s)
 {
     if (ndim == 2)
-        hipLaunchKernelGGL((k_face_tile<R, 2, 1, 1>), dim3(P.ntx * P.nty * P.nzc), dim3(64), 0, s, P);
+        hipLaunchKernelGGL((k_face_tile<R, 2, 1, 1, NP>), dim3(P.ntx * P.nty * P.nzc), dim3(64), 0, s, P);
     else
-        hipLaunchKernelGGL((k_face_tile<R, 3, 4, face_rows_per_thread(R)>), dim3(P.ntx * P.nty * P.nzc),
+        hipLaunchKernelGGL((k_face_tile<R, 3, 4, face_rows_per_thread(R, NP), NP>), dim3(P.ntx * P.nty * P.nzc),
                            dim3(256), 0, s, P);
+}
+
+template <int R>
+void launch_face_tile(int ndim, int np, FaceTileParams &P, hipStream_t s)
+{
+    if (np == 2) launch_face_tile_np<R, 2>(ndim, P, s);
+    else launch_face_tile_np<R, 1>(ndim, P, s);
 }
 
 // One thread per unique source node: S(x) += phi(x) sum_e coef_s[e] amp[pid[e]]
@@ -273,10 +291,10 @@ __global__ void k_vd_chain(Geom g, int r, int ndim, MidCoef c, const float *__re
 
 }  // namespace
 
-hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, const float *phi,
-                             const float *u, float *const *F, hipStream_t s)
+hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, int np,
+                             const float *const *phi, const float *const *u, float *const *F, hipStream_t s)
 {
-    if (r < 1 || r > 8) return hipErrorInvalidValue;
+    if (r < 1 || r > 8 || np < 1 || np > 2) return hipErrorInvalidValue;
     // faces of the grid nodes: z-marching tiles
     FaceTileParams T{};
     T.g = g;
@@ -285,36 +303,39 @@ hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const 
         T.sx[l] = sj[1][l];
         T.sy[l] = sj[2][l];
     }
-    T.phi = phi;
-    T.u = u;
+    for (int k = 0; k < np; ++k) {
+        T.phi[k] = phi[k];
+        T.u[k] = u[k];
+    }
     for (int a = 0; a < 3; ++a) T.F[a] = F[a];
-    const int tx = (ndim == 2) ? 1 : 4 * face_rows_per_thread(r);
+    const int tx = (ndim == 2) ? 1 : 4 * face_rows_per_thread(r, np);
     T.ntx = (g.X + tx - 1) / tx;
     T.nty = (g.Y + 63) / 64;
     T.zc = (ndim == 2) ? 16 : 32;
     T.nzc = (g.Z + T.zc - 1) / T.zc;
     switch (r) {
-    case 1: launch_face_tile<1>(ndim, T, s); break;
-    case 2: launch_face_tile<2>(ndim, T, s); break;
-    case 3: launch_face_tile<3>(ndim, T, s); break;
-    case 4: launch_face_tile<4>(ndim, T, s); break;
-    case 5: launch_face_tile<5>(ndim, T, s); break;
-    case 6: launch_face_tile<6>(ndim, T, s); break;
-    case 7: launch_face_tile<7>(ndim, T, s); break;
-    default: launch_face_tile<8>(ndim, T, s); break;
+    case 1: launch_face_tile<1>(ndim, np, T, s); break;
+    case 2: launch_face_tile<2>(ndim, np, T, s); break;
+    case 3: launch_face_tile<3>(ndim, np, T, s); break;
+    case 4: launch_face_tile<4>(ndim, np, T, s); break;
+    case 5: launch_face_tile<5>(ndim, np, T, s); break;
+    case 6: launch_face_tile<6>(ndim, np, T, s); break;
+    case 7: launch_face_tile<7>(ndim, np, T, s); break;
+    default: launch_face_tile<8>(ndim, np, T, s); break;
     }
-    // faces no grid node owns (m < 0 or m >= n along each axis)
+    // faces no grid node owns (m < 0 or m >= n along each axis), pair by pair
     const int n[3] = {g.Z, g.X, g.Y};
-    for (int axis = 0; axis < 3; ++axis) {
-        if (ndim == 2 && axis == 1) continue;
-        AxisCoef c{};
-        for (int l = 1; l <= r; ++l) c.s[l] = sj[axis][l];
-        int e[3] = {n[0], n[1], n[2]};
-        e[axis] = 2 * r - 1;
-        const int64_t total = int64_t(e[0]) * e[1] * e[2];
-        hipLaunchKernelGGL(k_face_image_outer, dim3(grid_blocks(total)), dim3(kBlock), 0, s, g, axis, r, c, phi,
-                           u, F[axis]);
-    }
+    for (int k = 0; k < np; ++k)
+        for (int axis = 0; axis < 3; ++axis) {
+            if (ndim == 2 && axis == 1) continue;
+            AxisCoef c{};
+            for (int l = 1; l <= r; ++l) c.s[l] = sj[axis][l];
+            int e[3] = {n[0], n[1], n[2]};
+            e[axis] = 2 * r - 1;
+            const int64_t total = int64_t(e[0]) * e[1] * e[2];
+            hipLaunchKernelGGL(k_face_image_outer, dim3(grid_blocks(total)), dim3(kBlock), 0, s, g, axis, r, c,
+                               phi[k], u[k], F[axis]);
+        }
     return hipGetLastError();
 }
 
