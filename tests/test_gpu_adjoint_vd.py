@@ -147,3 +147,37 @@ def test_vd_autograd_matches_adjoint():
     _, gv, gr, _, _ = _gpu_grads(n, so, nsteps, nbl, vel, rho, dt, src, rec, wav, d_obs, h, every=16)
     assert torch.equal(v.grad, gv)
     assert torch.equal(r.grad, gr)
+
+
+@pytest.mark.parametrize("n,so,nsteps,nbl,every", [
+    ((20, 23, 70), 2, 30, 0, 1),   # 3D, the shortest stencil, no layer, a checkpoint every step
+    ((48, 57), 2, 3, 4, 2),        # 2D, three steps
+    ((40, 37), 6, 25, 0, 4),       # 2D, no layer
+])
+def test_vd_gradients_edge_cases(n, so, nsteps, nbl, every):
+    vel, rho, dt, src, rec, wav, d_obs, h = _case(n, so, nsteps, nbl, seed=12)
+    # receivers five cells inside the grid, so that Kaiser-sinc footprints fit without a layer
+    ext = [10.0 * (k - 1) for k in n]
+    rec = np.array([[50.0 + (ext[a] - 100.0) * k / 9.0 for a in range(len(n))] for k in range(10)])
+    d_obs = 1e-4 * np.random.default_rng(3).standard_normal((nsteps, len(rec)))
+    args = (vel, rho, dt, src, rec, wav, d_obs, h)
+    print(f"case: VD adjoint edge n={n} SO{so} steps={nsteps} nbl={nbl} every={every}", flush=True)
+    gc_ref, grho_ref, gK_ref, tr_ref = _oracle_grads(n, so, nsteps, nbl, *args)
+    prop, gv, gr, gK, tr = _gpu_grads(n, so, nsteps, nbl, *args, every=every)
+    assert _rel(gv.double().cpu().numpy(), gc_ref) < 1e-3
+    assert _rel(gr.double().cpu().numpy(), grho_ref) < 1e-3
+
+
+def test_vd_zero_residual_gives_zero_gradients():
+    n, so, nsteps, nbl = (26, 31, 70), 4, 20, 3
+    vel, rho, dt, src, rec, wav, d_obs, h = _case(n, so, nsteps, nbl, seed=13)
+    prop = Propagator(n, h, so, dt, nsteps, scheme="vd_staggered", nbl=nbl)
+    prop.set_sources(src)
+    prop.set_receivers(rec)
+    prop.prepare(torch.from_numpy(vel).cuda(), torch.from_numpy(rho).cuda())
+    print("case: VD adjoint, zero residual", flush=True)
+    wt = torch.from_numpy(wav.astype(np.float32)).cuda()
+    fw = prop.forward(wt, checkpoint_every=7)
+    gv, _, gK, gr = prop.adjoint(wt, torch.zeros_like(fw.traces), fw.ckpt, 7)
+    torch.cuda.synchronize()
+    assert not torch.any(gv) and not torch.any(gr) and not torch.any(gK)

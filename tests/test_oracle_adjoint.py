@@ -228,3 +228,30 @@ def test_vd_dot_product(n):
     FTr = oracle.gradient_vd(st, s, src, rec, r, fw.history, nsrc=nsrc)[5]
     lhs, rhs = np.sum(fw.traces * r), np.sum(s * FTr)
     assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), abs(rhs))
+
+
+def test_vd_gradients_so2_single_step_and_no_layer():
+    # the shortest stencil, one time step, and no absorbing layer
+    for n, nbl, so, nt in [((24, 28), 3, 2, 30), ((24, 28), 0, 4, 1)]:
+        prob, c, rho, src, rec, nrec, wav, rng = _vd_setup(n=n, nbl=nbl, so=so, nt=nt)
+        d_obs = 1e-3 * rng.standard_normal((nt, nrec))
+        st = oracle.prepare(prob, c, rho)
+        fw = oracle.forward(st, wav, src, rec, nrec, keep_history=True)
+        gc, grho, *_ = oracle.gradient_vd(st, wav, src, rec, fw.traces - d_obs, fw.history)
+        d = rng.standard_normal(n)
+        for which, g, base in (("c", gc, c), ("rho", grho, rho)):
+            eps = 1e-6 * np.linalg.norm(base) / np.linalg.norm(d)
+            pa = (c + eps * d, rho) if which == "c" else (c, rho + eps * d)
+            ma = (c - eps * d, rho) if which == "c" else (c, rho - eps * d)
+            fd = (_vd_misfit(prob, *pa, src, rec, nrec, wav, d_obs) -
+                  _vd_misfit(prob, *ma, src, rec, nrec, wav, d_obs)) / (2 * eps)
+            an = np.sum(g * d)
+            assert abs(fd - an) < 2e-6 * max(abs(an), 1e-12), (n, so, nt, which, fd, an)
+
+
+def test_vd_gradient_of_zero_residual_is_zero():
+    prob, c, rho, src, rec, nrec, wav, _ = _vd_setup(n=(24, 28), nbl=2, so=4, nt=20)
+    st = oracle.prepare(prob, c, rho)
+    fw = oracle.forward(st, wav, src, rec, nrec, keep_history=True)
+    gc, grho, gK, gM, gb, _ = oracle.gradient_vd(st, wav, src, rec, np.zeros((20, nrec)), fw.history)
+    assert not np.any(gc) and not np.any(grho) and not np.any(gK) and not np.any(gM) and not np.any(gb)
