@@ -207,7 +207,7 @@ std::vector<int> zc_candidates(int Z, int r)
         const int zc = (Z + nz - 1) / nz;
         if (zc >= 4 * r || nz == 1) out.push_back(zc);
     }
-    for (int zc : {32, 48, 64, 96})
+    for (int zc : {32, 48, 64, 74, 96})
         if (zc < Z && zc >= 4 * r) out.push_back(zc);
     std::sort(out.begin(), out.end());
     out.erase(std::unique(out.begin(), out.end()), out.end());
@@ -366,9 +366,12 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     for (auto sh : shapes)
         for (int zc : zc_candidates(p->dims[0], p->r))
             for (int nt : {0, 1})
-                for (int pf : {1, 2}) {
+                for (int pf : {1, 2})
+                    for (int occ : {-1, 4}) {
+                // a cap of 4 blocks per CU is tried for single-step 4-wave block tiles
+                if (occ == 4 && (!const3 || sh.wt || sh.ts == 2 || sh.nw != 4 || p->ndim != 3)) continue;
                 if ((!const3 || sh.wt || sh.ts == 2) && pf == 2) continue;
-                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts, -1};
+                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts, occ};
                 st = sw_plan_set_tiling(p, &cand);
                 if (st != SW_OK) continue;
                 // per-step time: single sweeps, or two-step sweeps over half as many launches
