@@ -336,8 +336,10 @@ typedef struct sw_batch_io {
  * shots[s].field[nsteps_run % 2]. */
 sw_status sw_batch_forward(sw_batch *batch, const sw_batch_io *io, void *stream);
 
-/* Pick the tile shape (rows per tile, waves per block), the z-chunk length and
- * (for batches) the persistent grid size by timing a few steps of each
+/* Pick the tile shape (rows per tile, waves per block), the z-chunk length,
+ * cache policy and prefetch depth, for single plans also the two-step sweep
+ * (when io->field2 is given) and a cap of 4 resident blocks per CU, and (for
+ * batches) the persistent grid size, by timing a few steps of each
  * candidate on the given buffers (their contents are overwritten), or reuse
  * the choice stored under the same problem key in the JSON file `cache_path`
  * (may be NULL: no cache).  The choice is kept in the plan / batch and

@@ -383,7 +383,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
                 };
                 for (int w = 0; w < 2; ++w) SW_HIP(run());
                 SW_HIP(hipEventRecord(e0, s));
-                const int reps = 5;
+                const int reps = 10;
                 for (int k = 0; k < reps; ++k) SW_HIP(run());
                 SW_HIP(hipEventRecord(e1, s));
                 SW_HIP(hipEventSynchronize(e1));
