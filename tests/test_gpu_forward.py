@@ -161,3 +161,20 @@ def test_mirror_symmetry_bitwise(ndim):
     assert float(u.abs().max()) > 0
     for ax in range(ndim):
         assert torch.equal(u, torch.flip(u, dims=[ax]))
+
+
+def test_capped_kernel_first_launched_inside_graph_capture():
+    # a tiling whose kernel instance no other test launches, with a resident-block
+    # cap: its first launch (which reads the kernel's LDS size for the cap) happens
+    # inside graph capture; replays and the eager run must agree bit for bit
+    prop, wav = _simple_prop(n=(40, 44, 68), so=10, nsteps=30)
+    prop.set_tiling(16, 8, 9, 0, 2, occ=5)
+    print("case: occupancy-capped kernel first launched under graph capture", flush=True)
+    g = prop.forward(wav, use_graph=True)
+    g2 = prop.forward(wav, use_graph=True, fields=g.fields, traces=g.traces)
+    e = prop.forward(wav)
+    torch.cuda.synchronize()
+    for r in (g, g2):
+        assert torch.equal(e.traces, r.traces)
+        assert torch.equal(prop.grid_view(e.fields[e.current]), prop.grid_view(r.fields[r.current]))
+    prop.set_tiling()
