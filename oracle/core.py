@@ -195,9 +195,20 @@ def prepare(prob, vel, rho=None):
                  np.ascontiguousarray(A), np.ascontiguousarray(B), eta, aux)
 
 
-def geometry_table(prob, coords, interp="hicks", radius=4, kaiser_b=None):
-    """(nodes, ids, weights) on the extended grid for points given in metres."""
-    return geometry.weight_table(coords, prob.h, prob.nbl_lo, prob.N, interp, radius, kaiser_b)
+MIRROR_SIGN = {"none": None, "dirichlet": -1.0, "neumann": 1.0}
+
+
+def geometry_table(prob, coords, interp="hicks", radius=4, kaiser_b=None, role=None):
+    """(nodes, ids, weights) on the extended grid for points given in metres.
+    role ("source" or "receiver") says how a footprint crossing a side with a
+    mirror ghost condition is treated (image sources, ghost reads); it must be
+    given when the problem has such a side."""
+    mirror = [tuple(MIRROR_SIGN[b] for b in side) for side in prob.bc]
+    if any(s is not None for side in mirror for s in side):
+        if role not in ("source", "receiver"):
+            raise ValueError("geometry_table needs role='source' or 'receiver' with mirror ghost conditions")
+    return geometry.weight_table(coords, prob.h, prob.nbl_lo, prob.N, interp, radius, kaiser_b,
+                                 mirror=mirror, role=role or "receiver")
 
 
 def step(st, p, prev, lap_out=None):

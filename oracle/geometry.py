@@ -18,6 +18,19 @@ it: nodes floor(xi) and floor(xi)+1 with weights 1 - t and t, t = xi - floor(xi)
 Zero weights are dropped.  Coordinates are in metres from the first node of the
 physical grid; the returned node indices are on the extended grid (physical
 grid plus absorbing layer).
+
+Points near a side with a mirror ghost condition ("Boundary conditions and
+domain truncation": null Dirichlet / null Neumann by ghost nodes) follow the
+image method that defines those conditions: the grid is the half of a problem
+doubled about the boundary node, with the model mirrored evenly.
+* A source has an image across each mirrored side (reflected about the
+  boundary node, amplitude times -1 for Dirichlet, +1 for Neumann; across two
+  mirrored axes the image of the image).  The entries of the source and of its
+  images that fall inside the grid are the ones that act on it; entries beyond
+  a mirrored side belong to the other half.
+* A receiver reads ghost nodes as the ghost condition defines them: an entry
+  beyond a mirrored side reads its mirror node, times -1 for Dirichlet.
+An entry beyond a side without a mirror condition is an error.
 """
 import math
 import itertools
@@ -112,20 +125,81 @@ def point_weights(coord, h, nbl_lo, interp="hicks", radius=4, kaiser_b=None):
     return out
 
 
-def weight_table(coords, h, nbl_lo, N, interp="hicks", radius=4, kaiser_b=None):
+def _images(coord, h, nbl_lo, N, mirror):
+    """(coordinate, sign) of a source and its images across mirrored sides.
+    mirror[i] = (sign at the low side, sign at the high side), None where the
+    side has no mirror condition."""
+    out = [(list(coord), 1.0)]
+    for i, (lo_s, hi_s) in enumerate(mirror):
+        # boundary nodes of the extended grid, in metres from the physical origin
+        sides = [(lo_s, -nbl_lo[i] * h[i]), (hi_s, (N[i] - 1 - nbl_lo[i]) * h[i])]
+        new = []
+        for c, sg in out:
+            for sign, m in sides:
+                if sign is not None:
+                    d = list(c)
+                    d[i] = 2.0 * m - c[i]
+                    new.append((d, sg * sign))
+        out += new
+    return out
+
+
+def weight_table(coords, h, nbl_lo, N, interp="hicks", radius=4, kaiser_b=None, mirror=None,
+                 role="receiver"):
     """Flattened (node, point id, weight) arrays for a set of points on a grid
-    of extents N (extended grid); raises if a footprint leaves the grid."""
+    of extents N (extended grid).  mirror: per axis (low sign, high sign) of the
+    mirror ghost conditions (-1 Dirichlet, +1 Neumann, None without), or None;
+    role: "source" or "receiver" (how entries beyond a mirrored side are
+    treated).  Raises if a footprint leaves the grid across a side without a
+    mirror condition."""
+    ndim = len(N)
+    mirror = mirror or [(None, None)] * ndim
     nodes, ids, wts = [], [], []
+
+    def flat_of(idx):
+        f = 0
+        for k, n in zip(idx, N):
+            f = f * n + k
+        return f
+
+    def beyond(idx):
+        """Per axis: None inside the grid, else the mirror sign of the side crossed."""
+        out = []
+        for i, (k, n) in enumerate(zip(idx, N)):
+            if 0 <= k < n:
+                out.append(None)
+                continue
+            sign = mirror[i][0] if k < 0 else mirror[i][1]
+            if sign is None:
+                raise ValueError("point footprint leaves the grid")
+            out.append(sign)
+        return out
+
     for pid, coord in enumerate(coords):
-        for idx, w in point_weights(coord, h, nbl_lo, interp, radius, kaiser_b):
-            for k, n in zip(idx, N):
-                if k < 0 or k >= n:
-                    raise ValueError(f"point {pid} footprint leaves the grid")
-            flat = 0
-            for k, n in zip(idx, N):
-                flat = flat * n + k
-            nodes.append(flat)
-            ids.append(pid)
-            wts.append(w)
+        if role == "source":
+            for j, (c, sg) in enumerate(_images(coord, h, nbl_lo, N, mirror)):
+                for idx, w in point_weights(c, h, nbl_lo, interp, radius, kaiser_b):
+                    if j == 0:
+                        beyond(idx)          # the source itself may cross mirrored sides only
+                    if all(0 <= k < n for k, n in zip(idx, N)):
+                        nodes.append(flat_of(idx))
+                        ids.append(pid)
+                        wts.append(sg * w)
+        elif role == "receiver":
+            for idx, w in point_weights(coord, h, nbl_lo, interp, radius, kaiser_b):
+                signs = beyond(idx)
+                q = []
+                for k, n, sign in zip(idx, N, signs):
+                    if sign is not None:
+                        k = -k if k < 0 else 2 * (n - 1) - k
+                        if not 0 <= k < n:
+                            raise ValueError("point footprint reaches past the mirror of the grid")
+                        w = sign * w
+                    q.append(k)
+                nodes.append(flat_of(q))
+                ids.append(pid)
+                wts.append(w)
+        else:
+            raise ValueError(role)
     return (np.asarray(nodes, dtype=np.int64), np.asarray(ids, dtype=np.int64),
             np.asarray(wts, dtype=np.float64))

@@ -30,7 +30,11 @@
  *   none      -> 0
  *   dirichlet -> odd mirror about the boundary node (boundary node held at 0)
  *   neumann   -> even mirror about the boundary node
- * Model fields (b or rho) outside the grid take the nearest grid value.
+ * Model fields (b or rho) outside the grid: on a mirrored side the even
+ * mirror about the boundary node (the image of the model, so that the
+ * mirrored problem is the restriction of the problem doubled about that
+ * node, which is what the image method of the ghost conditions means); on a
+ * side without a mirror condition the nearest grid value.
  *
  * Arrays are C-ordered over (N0, N1, N2); a 2D grid uses N2 = 1 and ndim = 2.
  */
@@ -83,12 +87,18 @@ static double pval(const ow_grid *g, const double *p, const int64_t k[3])
     return sign * p[lin(g, q)];
 }
 
-/* Model value at node k: nearest grid node (edge replication). */
+/* Model value at node k: the even mirror about the boundary node on a side
+ * with a Dirichlet or Neumann condition, the nearest grid node (edge
+ * replication) on a side without one. */
 static double mval(const ow_grid *g, const double *a, const int64_t k[3])
 {
     int64_t q[3];
     for (int i = 0; i < 3; ++i) {
         int64_t x = k[i];
+        if (x < 0) x = (g->bc[i][0] != OW_BC_NONE) ? -x : 0;
+        if (x >= g->N[i]) x = (g->bc[i][1] != OW_BC_NONE) ? 2 * (g->N[i] - 1) - x : g->N[i] - 1;
+        /* a mirror reaching past the far side (fewer nodes than the stencil
+         * reach) falls back to the nearest node */
         if (x < 0) x = 0;
         if (x >= g->N[i]) x = g->N[i] - 1;
         q[i] = x;
@@ -121,7 +131,7 @@ static double d2(const ow_grid *g, const double *p, const int64_t k[3], int i)
 }
 
 /* Centred first derivative along axis i at node k; f is a wavefield (ghost
- * rule) when is_model == 0, a model field (edge replication) otherwise. */
+ * rule) when is_model == 0, a model field (model ghost rule) otherwise. */
 static double d1(const ow_grid *g, const double *f, const int64_t k[3], int i, int is_model)
 {
     double t = 0.0;

@@ -19,7 +19,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def _case(n, so, nbl, bc, scheme, nsteps, src, rec, seed):
+def _case(n, so, nbl, bc, scheme, nsteps, src, rec, seed, src_interp="linear"):
     rng = np.random.default_rng(seed)
     vel = (2200.0 + 300.0 * rng.random(n)).astype(np.float32)
     rho = (1500.0 + 800.0 * rng.random(n)).astype(np.float32) if scheme != "const" else None
@@ -29,10 +29,10 @@ def _case(n, so, nbl, bc, scheme, nsteps, src, rec, seed):
                           nbl=tuple(tuple(p) for p in nbl), bc=tuple(tuple(b) for b in bc))
     st = oracle.prepare(prob, vel.astype(np.float64), None if rho is None else rho.astype(np.float64))
     wav = oracle.ricker(18.0, dt, nsteps)[:, None]
-    ref = oracle.forward(st, wav, oracle.geometry_table(prob, src, "linear"),
-                         oracle.geometry_table(prob, rec, "linear"), len(rec))
+    ref = oracle.forward(st, wav, oracle.geometry_table(prob, src, src_interp, role="source"),
+                         oracle.geometry_table(prob, rec, "linear", role="receiver"), len(rec))
     prop = Propagator(n, h, so, dt, nsteps, scheme=scheme, nbl=[list(p) for p in nbl], bc=bc)
-    prop.set_sources(src, "linear")
+    prop.set_sources(src, src_interp)
     prop.set_receivers(rec, "linear")
     prop.prepare(torch.from_numpy(vel).cuda(), None if rho is None else torch.from_numpy(rho).cuda())
     w = torch.from_numpy(wav.astype(np.float32)).cuda()

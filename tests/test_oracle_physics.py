@@ -98,8 +98,8 @@ def _mms_run(scheme, so, h, c, u_expr, rho_expr, bc, L, tf, dt, receiver=None):
         return np.broadcast_to(f_fn(coords[0], coords[1], k * dt), shape)
 
     rec_pts = [receiver] if receiver is not None else []
-    fw = oracle.forward(st, None, oracle.geometry_table(prob, []),
-                        oracle.geometry_table(prob, rec_pts, "linear"), len(rec_pts),
+    fw = oracle.forward(st, None, oracle.geometry_table(prob, [], role="source"),
+                        oracle.geometry_table(prob, rec_pts, "linear", role="receiver"), len(rec_pts),
                         forcing=forcing)
     if receiver is not None:
         t = (np.arange(nt) + 1) * dt
