@@ -511,9 +511,10 @@ sw_status sw_plan_set_geometry(sw_plan *p, int32_t which, int32_t count, const d
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
     if (which != SW_SRC && which != SW_REC) return fail(SW_ERR_ARG, "which must be SW_SRC or SW_REC");
     sw_status st = build_points(p, which == SW_SRC ? p->src : p->rec, count, coords, interp, radius,
-                                kaiser_b);
+                                kaiser_b, which == SW_SRC);
     if (st != SW_OK) return st;
     p->prepared = false;
+    ++p->generation;
     return SW_OK;
 }
 
@@ -576,11 +577,11 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
     const Geom g = make_geom(p);
     float *K = at<float>(ws, p->ws.model_k);
     float *aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
-    SW_HIP(launch_model_prep(g, p->hz, p->hx, p->pad[0], p->prob.scheme, p->prob.dt, vel, rho, K, aux, s));
+    SW_HIP(launch_model_prep(g, p->bcm, p->hz, p->hx, p->pad[0], p->prob.scheme, p->prob.dt, vel, rho, K, aux, s));
     if (p->prob.scheme == SW_VD_STAGGERED) {
         StencilParams F;
         fill_params(p, ws, F);
-        SW_HIP(launch_face_buoyancy(g, p->hz, p->hx, p->pad[0], p->r, F.mj, aux,
+        SW_HIP(launch_face_buoyancy(g, p->bcm, p->hz, p->hx, p->pad[0], p->r, F.mj, aux,
                                     const_cast<float *>(F.face[0]), const_cast<float *>(F.face[1]),
                                     const_cast<float *>(F.face[2]), s));
     }
@@ -600,6 +601,7 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
                              1.0, s));
     p->prepared = true;
     p->prepared_ws = ws;
+    ++p->generation;
     return SW_OK;
 }
 
@@ -727,7 +729,8 @@ sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
         uint64_t(uintptr_t(io->field2[0])), uint64_t(uintptr_t(io->field2[1])),
         uint64_t(uintptr_t(io->traces)), uint64_t(uintptr_t(io->snaps)), uint64_t(io->saving_stride),
         uint64_t(uintptr_t(io->ckpt)), uint64_t(io->ckpt_every), uint64_t(io->step0),
-        uint64_t(io->nsteps_run)};
+        uint64_t(io->nsteps_run), p->generation, uint64_t(p->src.count), uint64_t(p->src.unode.size()),
+        uint64_t(p->rec.count), uint64_t(p->rec.node.size())};
     if (!p->graph_exec || p->graph_key != key) {
         if (p->graph_exec) {
             (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));

@@ -187,9 +187,11 @@ void write_cache(const char *path, const std::map<std::string, std::map<std::str
 
 std::string plan_key(const sw_plan *p, const char *kind)
 {
-    char buf[160];
-    std::snprintf(buf, sizeof(buf), "%s_s%d_r%d_d%d_%dx%dx%d", kind, p->prob.scheme, p->r, p->ndim,
-                  p->dims[0], p->dims[1], p->dims[2]);
+    // the ghost conditions are part of the key: mirrored sides rule out some tilings
+    char buf[200];
+    std::snprintf(buf, sizeof(buf), "%s_s%d_r%d_d%d_%dx%dx%d_bc%d%d%d%d%d%d", kind, p->prob.scheme, p->r, p->ndim,
+                  p->dims[0], p->dims[1], p->dims[2], p->bcm[0][0], p->bcm[0][1], p->bcm[1][0], p->bcm[1][1],
+                  p->bcm[2][0], p->bcm[2][1]);
     return buf;
 }
 
@@ -281,11 +283,17 @@ sw_status sw_batch_forward(sw_batch *b, const sw_batch_io *io, void *stream)
     if (st != SW_OK) return st;
     if (!io->use_graph) return enqueue_batch(b, io, s);
 
+    // the launches bake in the tiling, the persistent grid and the point
+    // maxima; the per-shot tables are read from the device table, which is
+    // uploaded before every launch
     std::vector<uint64_t> key = {uint64_t(uintptr_t(io->table)), uint64_t(io->nsteps_run),
                                  uint64_t(b->tiling.tx), uint64_t(b->tiling.nw), uint64_t(b->tiling.zc),
-                                 uint64_t(b->tiling.nt), uint64_t(b->bpc)};
+                                 uint64_t(b->tiling.nt), uint64_t(b->tiling.pf), uint64_t(b->bpc),
+                                 uint64_t(b->max_uniq), uint64_t(b->max_per_node), uint64_t(b->max_rec),
+                                 uint64_t(b->max_per_point)};
     for (int i = 0; i < b->nshots; ++i) {
         const sw_fwd_io &f = io->shots[i];
+        key.push_back(b->plans[i]->generation);
         for (const void *ptr : {static_cast<const void *>(f.workspace), static_cast<const void *>(f.wavelet),
                                 static_cast<const void *>(f.field[0]), static_cast<const void *>(f.field[1]),
                                 static_cast<const void *>(f.traces)})
@@ -337,7 +345,9 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
         auto &v = it->second;
         const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"], v["ts"],
                           v.count("occ") ? v["occ"] : -1};
-        return sw_plan_set_tiling(p, &t);
+        if (sw_plan_set_tiling(p, &t) == SW_OK) return SW_OK;
+        // a cached choice this plan rejects (a stale or hand-edited entry): tune again
+        set_error("");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     struct Shape { int tx, nw, wt, ts; };

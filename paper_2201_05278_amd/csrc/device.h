@@ -167,13 +167,18 @@ hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
 // inside the boundary node, along z, then x, then y.
 hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, float *field, hipStream_t s);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
-hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int scheme,
+// Model arrays over the padded layout; bcm (per internal axis and side, 0 for
+// zero ghosts) selects the even mirror image of the model in the ghosts of
+// mirrored sides, the nearest node elsewhere.
+hipError_t launch_model_prep(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int scheme,
                              double dt, const float *vel, const float *rho, float *K, float *aux,
                              hipStream_t s);
 // Staggered scheme: face buoyancies b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1})
-// along each axis (b at the nearest grid node), at every padded position.
-hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, int r, const float *mj,
-                                const float *b, float *fz, float *fx, float *fy, hipStream_t s);
+// along each axis (b at the model node: mirror image across mirrored sides,
+// nearest grid node elsewhere), at every padded position.
+hipError_t launch_face_buoyancy(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int r,
+                                const float *mj, const float *b, float *fz, float *fx, float *fy,
+                                hipStream_t s);
 // rho_inj (or NULL) scales the injection multiplier to dt^2 rho c^2; rho_rec
 // (or NULL) divides the recording weights by rho (see k_point_coef).
 hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel, const float *rho_inj,

@@ -14,6 +14,20 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Per internal axis (z, x, y) and side: non-zero where a mirror ghost
+// condition (Dirichlet or Neumann) holds.
+struct Sides {
+    int m[3][2];
+};
+
+Sides sides_of(const int (*bcm)[2])
+{
+    Sides sd{};
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 2; ++k) sd.m[a][k] = bcm ? bcm[a][k] != 0 : 0;
+    return sd;
+}
+
 __global__ void k_fill(float *__restrict__ p, int64_t n, float v)
 {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
@@ -28,9 +42,22 @@ __global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64
         d[i] = s[i];
 }
 
-// Every element of the padded arrays receives the model value of the nearest
-// physical node (edge replication into the layer, the halo and the row slack).
-__global__ void k_model_prep(Geom g, int hz, int hx, int pz, int scheme, float dt2,
+// Extended-grid coordinate v (axis extent n) mapped to the grid node whose
+// model value it takes: the even mirror about the boundary node on a side with
+// a Dirichlet or Neumann condition (the image of the model), then the nearest
+// node (edge replication; also where a mirror reaches past the far side).
+__device__ inline int model_node(int v, int n, int lo_mirror, int hi_mirror)
+{
+    if (v < 0 && lo_mirror) v = -v;
+    if (v >= n && hi_mirror) v = 2 * (n - 1) - v;
+    return min(max(v, 0), n - 1);
+}
+
+// Every element of the padded arrays receives a model value: the physical
+// node nearest to its model node (edge replication into the layer; mirror
+// images in the ghosts of mirrored sides; nearest node in the other ghosts and
+// the row slack).
+__global__ void k_model_prep(Geom g, Sides sd, int hz, int hx, int pz, int scheme, float dt2,
                              const float *__restrict__ vel, const float *__restrict__ rho,
                              float *__restrict__ K, float *__restrict__ aux)
 {
@@ -41,7 +68,9 @@ __global__ void k_model_prep(Geom g, int hz, int hx, int pz, int scheme, float d
         const int64_t t = i / g.py;
         const int xx = int(t % g.px);
         const int zz = int(t / g.px);
-        const int z = zz - hz, x = xx - hx, y = yy - 64;
+        const int z = model_node(zz - hz, g.Z, sd.m[0][0], sd.m[0][1]);
+        const int x = model_node(xx - hx, g.X, sd.m[1][0], sd.m[1][1]);
+        const int y = model_node(yy - 64, g.Y, sd.m[2][0], sd.m[2][1]);
         const int pzc = min(max(z - g.lo[0], 0), g.np[0] - 1);
         const int pxc = min(max(x - g.lo[1], 0), g.np[1] - 1);
         const int pyc = min(max(y - g.lo[2], 0), g.np[2] - 1);
@@ -96,21 +125,22 @@ __global__ void k_ghost_axis(Geom g, int axis, int lo, int hi, int depth, float 
 
 // Face buoyancies of the staggered operator at every padded position
 // (z, x, y): b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1}) along each axis, with
-// b read at the nearest node of the extended grid.  The sum runs j = 1..R with
-// fused multiply-adds in that order.
+// b read at the model node of the extended grid (mirror image on mirrored
+// sides, else the nearest node).  The sum runs j = 1..R with fused
+// multiply-adds in that order.
 struct FaceCoef {
     float m[9];
 };
 
-__global__ void k_face_buoyancy(Geom g, int hz, int hx, int pz, int r, FaceCoef c,
+__global__ void k_face_buoyancy(Geom g, Sides sd, int hz, int hx, int pz, int r, FaceCoef c,
                                 const float *__restrict__ b, float *__restrict__ fz,
                                 float *__restrict__ fx, float *__restrict__ fy)
 {
     const int64_t total = int64_t(pz) * g.px * g.py;
     auto at = [&](int z, int x, int y) -> float {
-        z = min(max(z, 0), g.Z - 1);
-        x = min(max(x, 0), g.X - 1);
-        y = min(max(y, 0), g.Y - 1);
+        z = model_node(z, g.Z, sd.m[0][0], sd.m[0][1]);
+        x = model_node(x, g.X, sd.m[1][0], sd.m[1][1]);
+        y = model_node(y, g.Y, sd.m[2][0], sd.m[2][1]);
         return b[g.origin + (int64_t(z) * g.px + x) * g.py + y];
     };
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
@@ -348,12 +378,12 @@ hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_model_prep(const Geom &g, int halo_z, int halo_x, int pz, int scheme, double dt,
-                             const float *vel, const float *rho, float *K, float *aux,
+hipError_t launch_model_prep(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int scheme,
+                             double dt, const float *vel, const float *rho, float *K, float *aux,
                              hipStream_t s)
 {
     const int64_t total = int64_t(pz) * g.px * g.py;
-    hipLaunchKernelGGL(k_model_prep, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, halo_z,
+    hipLaunchKernelGGL(k_model_prep, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, sides_of(bcm), halo_z,
                        halo_x, pz, scheme, float(dt * dt), vel, rho, K, aux);
     return hipGetLastError();
 }
@@ -373,13 +403,15 @@ hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, floa
     return hipSuccess;
 }
 
-hipError_t launch_face_buoyancy(const Geom &g, int halo_z, int halo_x, int pz, int r, const float *mj,
-                                const float *b, float *fz, float *fx, float *fy, hipStream_t s)
+hipError_t launch_face_buoyancy(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int r,
+                                const float *mj, const float *b, float *fz, float *fx, float *fy,
+                                hipStream_t s)
 {
     FaceCoef c{};
     for (int l = 1; l <= r; ++l) c.m[l] = mj[l];
     const int64_t total = int64_t(pz) * g.px * g.py;
-    hipLaunchKernelGGL(k_face_buoyancy, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, halo_z, halo_x, pz,
+    hipLaunchKernelGGL(k_face_buoyancy, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, sides_of(bcm), halo_z,
+                       halo_x, pz,
                        r, c, b, fz, fx, fy);
     return hipGetLastError();
 }

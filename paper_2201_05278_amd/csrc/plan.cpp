@@ -221,7 +221,7 @@ static void axis_weights(double xi, int interp, int radius, double b, std::vecto
 }
 
 sw_status build_points(sw_plan *p, PointSet &ps, int count, const double *coords, int interp,
-                       int radius, double kaiser_b)
+                       int radius, double kaiser_b, bool source)
 {
     const sw_problem &q = p->prob;
     if (count < 0) return fail(SW_ERR_ARG, "point count must be >= 0");
@@ -247,47 +247,97 @@ sw_status build_points(sw_plan *p, PointSet &ps, int count, const double *coords
     int axmap[3];
     if (q.ndim == 3) { axmap[0] = 0; axmap[1] = 1; axmap[2] = 2; }
     else { axmap[0] = 0; axmap[1] = 2; axmap[2] = -1; }
+    // a point and, for a source, its images across sides with a mirror ghost
+    // condition: the problem doubled about the boundary node of such a side
+    // carries the source reflected about that node, times -1 (Dirichlet) or
+    // +1 (Neumann); across two mirrored sides, the image of the image
+    struct Image {
+        double c[3];
+        double sign;
+    };
+    std::vector<Image> imgs;
     std::vector<AxisW> aw[3];
     for (int pt = 0; pt < count; ++pt) {
-        for (int i = 0; i < 3; ++i) aw[i].assign(1, AxisW{0, 1.0});
+        Image o{{0.0, 0.0, 0.0}, 1.0};
         for (int a = 0; a < q.ndim; ++a) {
-            const int ia = axmap[a];
             const double c = coords[size_t(pt) * q.ndim + a];
             const double ext = double(q.n[a] - 1) * q.h[a];
             if (!(c >= 0.0 && c <= ext))
                 return fail(SW_ERR_DOMAIN, "point " + std::to_string(pt) +
                                                " lies outside the physical grid");
-            axis_weights(c / q.h[a], interp, radius, kaiser_b, aw[ia]);
-            for (auto &e : aw[ia]) {
-                const int k = e.k + p->lo[ia];
-                if (k < 0 || k >= p->dims[ia])
-                    return fail(SW_ERR_DOMAIN, "footprint of point " + std::to_string(pt) +
-                                                   " leaves the extended grid");
-            }
+            o.c[a] = c;
         }
-        for (auto &ez : aw[0])
-            for (auto &ex : aw[1])
-                for (auto &ey : aw[2]) {
-                    const int z = ez.k + p->lo[0], x = ex.k + p->lo[1], y = ey.k + p->lo[2];
-                    const double w = ez.w * ex.w * ey.w;
-                    if (w == 0.0) continue;
-                    out.node.push_back(p->origin + (int64_t(z) * p->pad[1] + x) * p->pad[2] + y);
-                    out.pid.push_back(pt);
-                    // squared distance (cells) from the node to the physical box
-                    int64_t d2 = 0;
-                    const int c3[3] = {z, x, y};
-                    int64_t phys = 0;
-                    for (int i = 0; i < 3; ++i) {
-                        const int e = std::max(0, std::max(p->lo[i] - c3[i],
-                                                           c3[i] - (p->lo[i] + p->nphys[i] - 1)));
-                        d2 += int64_t(e) * e;
-                        const int pc = std::min(std::max(c3[i] - p->lo[i], 0), p->nphys[i] - 1);
-                        phys = phys * p->nphys[i] + pc;
+        imgs.assign(1, o);
+        if (source)
+            for (int a = 0; a < q.ndim; ++a) {
+                const int ia = axmap[a];
+                const size_t n0 = imgs.size();
+                for (size_t j = 0; j < n0; ++j)
+                    for (int side = 0; side < 2; ++side) {
+                        const int bc = p->bcm[ia][side];
+                        if (!bc) continue;
+                        // boundary node of the extended grid, metres from physical node 0
+                        const double m = side == 0 ? -double(p->lo[ia]) * q.h[a]
+                                                   : double(p->dims[ia] - 1 - p->lo[ia]) * q.h[a];
+                        Image im = imgs[j];
+                        im.c[a] = 2.0 * m - imgs[j].c[a];
+                        im.sign = imgs[j].sign * (bc == SW_BC_DIRICHLET ? -1.0 : 1.0);
+                        imgs.push_back(im);
                     }
-                    out.d2.push_back(int32_t(d2));
-                    out.phys.push_back(phys);
-                    out.weight.push_back(float(w));
+            }
+        for (size_t j = 0; j < imgs.size(); ++j) {
+            for (int i = 0; i < 3; ++i) aw[i].assign(1, AxisW{0, 1.0});
+            for (int a = 0; a < q.ndim; ++a) {
+                const int ia = axmap[a];
+                axis_weights(imgs[j].c[a] / q.h[a], interp, radius, kaiser_b, aw[ia]);
+                std::vector<AxisW> kept;
+                for (auto &e : aw[ia]) {
+                    int k = e.k + p->lo[ia];
+                    double w = e.w;
+                    if (k < 0 || k >= p->dims[ia]) {
+                        const int bc = p->bcm[ia][k < 0 ? 0 : 1];
+                        if (j == 0 && !bc)
+                            return fail(SW_ERR_DOMAIN, "footprint of point " + std::to_string(pt) +
+                                                           " leaves the extended grid");
+                        // a source's entries beyond a mirrored side belong to
+                        // the other half of the doubled problem
+                        if (source) continue;
+                        // a receiver reads the ghost node: its mirror node,
+                        // times -1 across a Dirichlet side
+                        k = k < 0 ? -k : 2 * (p->dims[ia] - 1) - k;
+                        if (k < 0 || k >= p->dims[ia])
+                            return fail(SW_ERR_DOMAIN, "footprint of point " + std::to_string(pt) +
+                                                           " reaches past the mirror of the grid");
+                        if (bc == SW_BC_DIRICHLET) w = -w;
+                    }
+                    kept.push_back({k - p->lo[ia], w});
                 }
+                aw[ia].swap(kept);
+            }
+            for (auto &ez : aw[0])
+                for (auto &ex : aw[1])
+                    for (auto &ey : aw[2]) {
+                        const int z = ez.k + p->lo[0], x = ex.k + p->lo[1], y = ey.k + p->lo[2];
+                        const double w = imgs[j].sign * ez.w * ex.w * ey.w;
+                        if (w == 0.0) continue;
+                        out.node.push_back(p->origin + (int64_t(z) * p->pad[1] + x) * p->pad[2] + y);
+                        out.pid.push_back(pt);
+                        // squared distance (cells) from the node to the physical box
+                        int64_t d2 = 0;
+                        const int c3[3] = {z, x, y};
+                        int64_t phys = 0;
+                        for (int i = 0; i < 3; ++i) {
+                            const int e = std::max(0, std::max(p->lo[i] - c3[i],
+                                                               c3[i] - (p->lo[i] + p->nphys[i] - 1)));
+                            d2 += int64_t(e) * e;
+                            const int pc = std::min(std::max(c3[i] - p->lo[i], 0), p->nphys[i] - 1);
+                            phys = phys * p->nphys[i] + pc;
+                        }
+                        out.d2.push_back(int32_t(d2));
+                        out.phys.push_back(phys);
+                        out.weight.push_back(float(w));
+                    }
+        }
         out.ptr.push_back(int32_t(out.node.size()));
         out.max_per_point = std::max(out.max_per_point, out.ptr[pt + 1] - out.ptr[pt]);
     }

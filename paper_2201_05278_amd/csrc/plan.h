@@ -93,6 +93,9 @@ struct sw_plan {
     // stencil tiling chosen by sw_plan_set_tiling / sw_plan_autotune (tx == 0: default)
     int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = -1, tile_pf = 0, tile_wt = 0, tile_ts = 0,
         tile_occ = -1;
+    // bumped by every call that changes what a captured launch bakes in
+    // (point tables and counts, model, tiling); part of the graph keys
+    uint64_t generation = 1;
     // cached HIP graph of a forward run, captured on a private stream
     void *graph_exec = nullptr;
     void *capture_stream = nullptr;
@@ -102,7 +105,9 @@ struct sw_plan {
 namespace sw {
 sw_status build_layout(sw_plan *p);
 void build_workspace_map(sw_plan *p);
+// source: true for the source table (images across mirrored sides), false
+// for receivers (ghost reads across mirrored sides).
 sw_status build_points(sw_plan *p, PointSet &ps, int count, const double *coords, int interp,
-                       int radius, double kaiser_b);
+                       int radius, double kaiser_b, bool source);
 double a1d(int space_order);
 }  // namespace sw

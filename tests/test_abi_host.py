@@ -51,7 +51,8 @@ def test_ricker_matches_oracle():
 
 def _compare_tables(prop, prob, which, coords, interp, radius=4):
     nodes, ids, w = prop.point_table(which)
-    ref_nodes, ref_ids, ref_w = oracle.geometry_table(prob, coords, interp, radius)
+    ref_nodes, ref_ids, ref_w = oracle.geometry_table(prob, coords, interp, radius,
+                                                      role="source" if which == "src" else "receiver")
     lay = prop.layout
     # map padded-layout offsets back to extended-grid flat indices
     off = nodes - lay.origin
@@ -84,6 +85,41 @@ def test_point_tables_match_oracle(interp, ndim):
     prop.set_receivers(coords[::-1], interp)
     _compare_tables(prop, prob, "src", coords, interp)
     _compare_tables(prop, prob, "rec", coords[::-1], interp)
+
+
+@pytest.mark.parametrize("interp", ["hicks", "linear"])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_point_tables_with_mirror_sides_match_oracle(interp, ndim):
+    # footprints crossing Dirichlet / Neumann sides: sources take their images,
+    # receivers read ghosts (as the image method of those conditions defines)
+    n = (30, 41, 37)[:ndim]
+    h = (10.0, 12.0, 8.0)[:ndim]
+    nbl = ((0, 7), (0, 0), (3, 0))[:ndim]
+    bc = (("dirichlet", "none"), ("neumann", "dirichlet"), ("none", "neumann"))[:ndim]
+    prob = oracle.Problem(n=n, h=h, space_order=8, dt=1e-3, nsteps=10, nbl=nbl, bc=bc)
+    prop = Propagator(n, h, 8, 1e-3, 10, nbl=[list(x) for x in nbl], bc=[list(b) for b in bc])
+    rng = np.random.default_rng(2)
+    ext = (np.array(n) - 1) * np.array(h)
+    coords = rng.uniform(0.2, 0.8, size=(6, ndim)) * ext
+    coords[0, 0] = 1.3 * h[0]                 # near the Dirichlet top
+    coords[1, 0] = 0.0                        # on it
+    coords[2, 1] = 0.4 * h[1]                 # near the second axis' low side
+    coords[3, 1] = ext[1] - 0.7 * h[1]        # near its high side
+    coords[4, 0] = 2.2 * h[0]
+    coords[4, 1] = 1.6 * h[1]                 # near a corner of two mirrored sides
+    prop.set_sources(coords, interp)
+    prop.set_receivers(coords[::-1], interp)
+    _compare_tables(prop, prob, "src", coords, interp)
+    _compare_tables(prop, prob, "rec", coords[::-1], interp)
+    # a window reaching past the mirror of a short axis is refused on both sides
+    short = (6,) + tuple(n[1:])
+    prob_s = oracle.Problem(n=short, h=h, space_order=8, dt=1e-3, nsteps=10, nbl=((0, 0),) + nbl[1:], bc=bc)
+    prop_s = Propagator(short, h, 8, 1e-3, 10, nbl=[[0, 0]] + [list(x) for x in nbl[1:]],
+                        bc=[list(b) for b in bc])
+    pt = [[2.5 * h[0]] + [0.5 * e for e in ext[1:]]]
+    with pytest.raises(ValueError):
+        oracle.geometry_table(prob_s, pt, "hicks", 4, role="receiver")
+    _expect("SW_ERR_DOMAIN", prop_s.set_receivers, pt, "hicks")
 
 
 def test_layout_is_aligned_and_padded():
