@@ -64,6 +64,17 @@ __device__ inline bool axis_read(int v, int n, int lo, int hi, int h)
     return (v >= 0 && v < n) || (v < 0 && lo != 0 && v >= -h) || (v >= n && hi != 0 && v < n + h);
 }
 
+// Grid node whose model value coordinate v (axis extent n) takes: the even
+// mirror about the boundary node across a side with a mirror condition (lo /
+// hi non-zero: the image of the model), then the nearest node (edge
+// replication; also where a mirror reaches past the far side).
+__host__ __device__ inline int model_axis(int v, int n, int lo, int hi)
+{
+    if (v < 0 && lo) v = -v;
+    if (v >= n && hi) v = 2 * (n - 1) - v;
+    return v < 0 ? 0 : (v > n - 1 ? n - 1 : v);
+}
+
 // Whether coordinate v lies on a side held at zero by a Dirichlet condition.
 __device__ inline bool axis_dirichlet(int v, int n, int lo, int hi)
 {

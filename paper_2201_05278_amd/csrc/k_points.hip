@@ -42,17 +42,6 @@ __global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64
         d[i] = s[i];
 }
 
-// Extended-grid coordinate v (axis extent n) mapped to the grid node whose
-// model value it takes: the even mirror about the boundary node on a side with
-// a Dirichlet or Neumann condition (the image of the model), then the nearest
-// node (edge replication; also where a mirror reaches past the far side).
-__device__ inline int model_node(int v, int n, int lo_mirror, int hi_mirror)
-{
-    if (v < 0 && lo_mirror) v = -v;
-    if (v >= n && hi_mirror) v = 2 * (n - 1) - v;
-    return min(max(v, 0), n - 1);
-}
-
 // Every element of the padded arrays receives a model value: the physical
 // node nearest to its model node (edge replication into the layer; mirror
 // images in the ghosts of mirrored sides; nearest node in the other ghosts and
@@ -68,9 +57,9 @@ __global__ void k_model_prep(Geom g, Sides sd, int hz, int hx, int pz, int schem
         const int64_t t = i / g.py;
         const int xx = int(t % g.px);
         const int zz = int(t / g.px);
-        const int z = model_node(zz - hz, g.Z, sd.m[0][0], sd.m[0][1]);
-        const int x = model_node(xx - hx, g.X, sd.m[1][0], sd.m[1][1]);
-        const int y = model_node(yy - 64, g.Y, sd.m[2][0], sd.m[2][1]);
+        const int z = model_axis(zz - hz, g.Z, sd.m[0][0], sd.m[0][1]);
+        const int x = model_axis(xx - hx, g.X, sd.m[1][0], sd.m[1][1]);
+        const int y = model_axis(yy - 64, g.Y, sd.m[2][0], sd.m[2][1]);
         const int pzc = min(max(z - g.lo[0], 0), g.np[0] - 1);
         const int pxc = min(max(x - g.lo[1], 0), g.np[1] - 1);
         const int pyc = min(max(y - g.lo[2], 0), g.np[2] - 1);
@@ -138,9 +127,9 @@ __global__ void k_face_buoyancy(Geom g, Sides sd, int hz, int hx, int pz, int r,
 {
     const int64_t total = int64_t(pz) * g.px * g.py;
     auto at = [&](int z, int x, int y) -> float {
-        z = model_node(z, g.Z, sd.m[0][0], sd.m[0][1]);
-        x = model_node(x, g.X, sd.m[1][0], sd.m[1][1]);
-        y = model_node(y, g.Y, sd.m[2][0], sd.m[2][1]);
+        z = model_axis(z, g.Z, sd.m[0][0], sd.m[0][1]);
+        x = model_axis(x, g.X, sd.m[1][0], sd.m[1][1]);
+        y = model_axis(y, g.Y, sd.m[2][0], sd.m[2][1]);
         return b[g.origin + (int64_t(z) * g.px + x) * g.py + y];
     };
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;

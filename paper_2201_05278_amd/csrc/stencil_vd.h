@@ -27,7 +27,6 @@
 
 namespace sw {
 
-__device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 template <int R, int NDIM, int TX, int NW, int NT, int MODE = MODE_FWD>
 __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
@@ -342,7 +341,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
     const int ze = min(zb + P.zc, g.Z);
     const int64_t sz = int64_t(g.px) * g.py;
     const bool yin = y < g.Y;
-    const int yc = clampi(y, 0, g.Y - 1);
+    const int yc = model_axis(y, g.Y, P.bcm[2][0], P.bcm[2][1]);   // model reads: mirror images / nearest node
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
     // plane base pointers + unsigned 32-bit lane offsets off(x, y) = xy0 + x py + y
     auto off = [&](int x, int yy) -> unsigned { return unsigned(g.xy0 + x * g.py + yy); };
@@ -369,7 +368,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         rpo[i] = rp[i] ? off(x, y) : 0u;
         rdir[i] = axis_dirichlet(x, g.X, P.bcm[1][0], P.bcm[1][1]) ||
                   axis_dirichlet(y, g.Y, P.bcm[2][0], P.bcm[2][1]);
-        rroff[i] = off(clampi(x, 0, g.X - 1), yc);
+        rroff[i] = off(model_axis(x, g.X, P.bcm[1][0], P.bcm[1][1]), yc);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = ex * ex + ey * ey;
     }
@@ -384,7 +383,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         hxin[s] = hxok[s] && pread(x, y);
         hxrow[s] = (hr < R) ? hr : TX + hr;
         hxo[s] = hxin[s] ? off(x, y) : 0u;
-        hxro[s] = off(clampi(x, 0, g.X - 1), yc);
+        hxro[s] = off(model_axis(x, g.X, P.bcm[1][0], P.bcm[1][1]), yc);
     }
     unsigned hyo[YHN], hyro[YHN];
     bool hyin[YHN], hyok[YHN];
@@ -400,7 +399,8 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         hyrow[s] = HXR + row;
         hycol[s] = (c < R) ? c : 64 + c;
         hyo[s] = hyin[s] ? off(x, yy) : 0u;
-        hyro[s] = off(clampi(x, 0, g.X - 1), clampi(yy, 0, g.Y - 1));
+        hyro[s] = off(model_axis(x, g.X, P.bcm[1][0], P.bcm[1][1]),
+                     model_axis(yy, g.Y, P.bcm[2][0], P.bcm[2][1]));
     }
 
     float q[RPT][2 * R + 1], qr[RPT][2 * R + 1];
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
         for (int k = 0; k < 2 * R; ++k) {
             const int z = zb - R + k;
             q[i][k] = (rp[i] && zread(z)) ? (cur + int64_t(z) * sz)[rpo[i]] : 0.0f;
-            qr[i][k] = (rm + int64_t(clampi(z, 0, g.Z - 1)) * sz)[rroff[i]];
+            qr[i][k] = (rm + int64_t(model_axis(z, g.Z, P.bcm[0][0], P.bcm[0][1])) * sz)[rroff[i]];
         }
 
     float nf[RPT], nfr[RPT], np_[RPT], nk[RPT], na[RPT], nb[RPT];
@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             nf[i] = (rp[i] && zread(zf)) ? cur[rpo[i] + int64_t(zf) * sz] : 0.0f;
-            nfr[i] = rm[rroff[i] + int64_t(min(zf, g.Z - 1)) * sz];
+            nfr[i] = rm[rroff[i] + int64_t(model_axis(zf, g.Z, P.bcm[0][0], P.bcm[0][1])) * sz];
             np_[i] = rin[i] ? ld_stream<NT>(nxt + zo + roff[i]) : 0.0f;
             nk[i] = rin[i] ? ld_stream<NT>(km + zo + roff[i]) : 0.0f;
             const int d2 = ez * ez + ex2[i];

@@ -10,6 +10,7 @@ import pytest
 import torch
 
 import oracle
+from tests._parity import assert_traces
 import workloads
 from paper_2201_05278_amd import Propagator
 
@@ -56,7 +57,7 @@ def test_homogeneous_2d_full_size():
     print(f"case: homogeneous_2d {wl.n} SO{wl.space_order} {wl.nsteps} steps", flush=True)
     ref, res, prop, _ = run_pair(wl.n, wl.h, wl.space_order, wl.nbl, wl.nsteps, wl.vel, wl.src,
                                  wl.rec, f=wl.f_peak)
-    assert rel(res.traces.cpu().numpy(), ref.traces) < TOL
+    assert_traces(res.traces, ref.traces)
     assert rel(field_np(prop, res), ref.p) < TOL
 
 
@@ -72,7 +73,7 @@ def test_layered_3d_ragged_tiles(so):
     src = np.array([[123.3, 221.7, 345.2]])
     rec = np.array([[0.0, 10.0 * k, 7.0 * k + 3.3] for k in range(40)])
     ref, res, prop, _ = run_pair(n, h, so, 8, 140, vel, src, rec, f=18.0)
-    assert rel(res.traces.cpu().numpy(), ref.traces) < TOL
+    assert_traces(res.traces, ref.traces)
     assert rel(field_np(prop, res), ref.p) < TOL
 
 
@@ -85,7 +86,7 @@ def test_smooth_3d_trilinear_points():
     rec = np.array([[24.6, 5.0 + 20.0 * i, 5.0 + 15.0 * j] for i in range(20) for j in range(20)])
     ref, res, prop, _ = run_pair(n, h, 8, (( 6, 9), (7, 5), (10, 4)), 120, vel, src, rec,
                                  "linear", "linear", f=12.0)
-    assert rel(res.traces.cpu().numpy(), ref.traces) < TOL
+    assert_traces(res.traces, ref.traces)
 
 
 def test_2d_uneven_layer_and_snapshots():
@@ -96,7 +97,7 @@ def test_2d_uneven_layer_and_snapshots():
     rec = np.array([[25.0, 7.5 * k] for k in range(0, 129, 4)])
     ref, res, prop, _ = run_pair(n, h, 6, ((0, 30), (25, 12)), 200, vel, src, rec, f=20.0,
                                  saving_stride=50)
-    assert rel(res.traces.cpu().numpy(), ref.traces) < TOL
+    assert_traces(res.traces, ref.traces)
     assert res.snaps.shape[0] == 4
     for k in range(4):
         assert rel(res.snaps[k].double().cpu().numpy(), ref.snaps[k]) < TOL
