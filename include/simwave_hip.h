@@ -25,7 +25,7 @@
  *       p^{n+1} = A (2 p^n + K (L p^n)) - B p^{n-1},
  *       A = 1/(1 + eta dt),  B = (1 - eta dt)/(1 + eta dt),
  *     with p^{-1} = p^0 = 0;
- *   - the spatial operator L of space order SO = 2r (even, 2..16):
+ *   - the spatial operator L of space order SO = 2r (even, 2..20):
  *       SW_CONST        centred Laplacian, K = dt^2 c^2;
  *       SW_VD_CENTRED   Laplacian minus (grad rho / rho) . grad p with centred
  *                       first derivatives (the paper's expanded
@@ -86,7 +86,7 @@ typedef struct sw_problem {
     int32_t ndim;           /* 2 or 3 */
     int32_t n[3];           /* physical nodes per axis (z, x[, y]); unused axis: 1 */
     double  h[3];           /* grid spacing per axis, metres */
-    int32_t space_order;    /* even, 2..16 */
+    int32_t space_order;    /* even, 2..20 (paper, "Space discretization") */
     int32_t scheme;         /* SW_CONST, SW_VD_STAGGERED or SW_VD_CENTRED */
     int32_t nbl[3][2];      /* absorbing layer cells (low side, high side) per axis */
     int32_t bc[3][2];       /* ghost condition per side at the edge of the extended grid
@@ -224,6 +224,11 @@ typedef struct sw_fwd_io {
                                  time: field -> field2 -> field); remaining steps and
                                  all other cases run singly.  Contents on return are
                                  unspecified; the result is in field[] as above. */
+    int32_t check_finite;     /* 1: after the run, count the non-finite values among the
+                                 trace rows written and the final wavefield p^{end}
+                                 (waits for the stream); the call then returns
+                                 SW_ERR_NONFINITE if there are any (an unstable dt or
+                                 model), with the count in the error message */
 } sw_fwd_io;
 
 sw_status sw_forward(sw_plan *plan, const sw_fwd_io *io, void *stream);

@@ -57,5 +57,7 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int64)
         L.ow_step_points.argtypes = [gp, ctypes.c_int32, dp, dp, dp, dp, dp, dp, ip, ctypes.c_int64, dp]
         L.ow_step_points.restype = None
+        L.ow_threads.argtypes = []
+        L.ow_threads.restype = ctypes.c_int32
         _lib = L
     return _lib

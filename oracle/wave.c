@@ -41,6 +41,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <omp.h>
 
 enum { OW_CONST = 0, OW_VD_STAGGERED = 1, OW_VD_CENTRED = 2 };
 enum { OW_BC_NONE = 0, OW_BC_DIRICHLET = 1, OW_BC_NEUMANN = 2 };
@@ -256,3 +257,6 @@ void ow_step_points(const ow_grid *g, int32_t scheme, const double *p, const dou
     for (int64_t s = 0; s < n; ++s)
         out[s] = update_at(g, scheme, p, prev, K, A, B, aux, idx[s], 0);
 }
+
+/* Threads the parallel loops above run with (for timing reports). */
+int32_t ow_threads(void) { return (int32_t)omp_get_max_threads(); }

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsimwave_hip.so")
 SOURCES = ["plan.cpp", "api.cpp", "batch.cpp", "k_dispatch.cpp", "k_points.hip", "k_adjoint_vd.hip"] + \
-          [f"k_r{r}.hip" for r in range(1, 9)]
+          [f"k_r{r}.hip" for r in range(1, 11)]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in device code

@@ -55,7 +55,7 @@ class FwdIO(ctypes.Structure):
                 ("traces", c_void_p), ("snaps", c_void_p), ("saving_stride", c_int32),
                 ("ckpt", c_void_p), ("ckpt_every", c_int32), ("step0", c_int32),
                 ("nsteps_run", c_int32), ("use_graph", c_int32), ("stencil_ms", c_float_p),
-                ("field2", c_void_p * 2)]
+                ("field2", c_void_p * 2), ("check_finite", c_int32)]
 
 
 class AdjIO(ctypes.Structure):

@@ -79,7 +79,8 @@ bool wave_shape_ok(int tx, int nw)
 
 bool vd_shape_ok(int tx, int nw)
 {
-    return (tx == 16 && nw == 8) || (tx == 8 && nw == 8) || (tx == 8 && nw == 4) || (tx == 16 && nw == 4);
+    return (tx == 16 && nw == 8) || (tx == 8 && nw == 8) || (tx == 8 && nw == 4) || (tx == 16 && nw == 4) ||
+           (tx == 16 && nw == 16);
 }
 
 // Two-step sweep shapes whose register queues fit (same rule as the kernel).
@@ -120,7 +121,7 @@ static ConstDefault const_default(int r)
     if (r <= 2) return {8, 4, 4};
     if (r <= 5) return {24, 8, 0};
     if (r == 6) return {16, 4, 3};
-    return {8, 4, 0};
+    return {8, 4, 0};            // r = 7 .. 10
 }
 
 Tiling choose_tiling(const sw_plan *p)
@@ -176,7 +177,6 @@ void fill_params(const sw_plan *p, void *ws, StencilParams &P)
     P.g = make_geom(p);
     P.K = at<float>(ws, p->ws.model_k);
     P.aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
-    for (int a = 0; a < 3; ++a) P.face[a] = p->ws.face[a] ? at<float>(ws, p->ws.face[a]) : nullptr;
     P.damp = at<float2>(ws, p->ws.damp);
     P.ndamp = p->damp_n;
     for (int a = 0; a < 3; ++a)
@@ -270,8 +270,8 @@ sw_status check_problem(const sw_problem *q)
 {
     if (!q) return fail(SW_ERR_ARG, "problem is NULL");
     if (q->ndim != 2 && q->ndim != 3) return fail(SW_ERR_UNSUPPORTED, "ndim must be 2 or 3");
-    if (q->space_order < 2 || q->space_order > 16 || q->space_order % 2)
-        return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..16");
+    if (q->space_order < 2 || q->space_order > 20 || q->space_order % 2)
+        return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..20");
     if (q->scheme != SW_CONST && q->scheme != SW_VD_STAGGERED && q->scheme != SW_VD_CENTRED)
         return fail(SW_ERR_ARG, "unknown scheme");
     const int r = q->space_order / 2;
@@ -330,8 +330,8 @@ sw_status sw_critical_dt(int32_t ndim, const double *h, int32_t space_order, dou
 {
     set_error("");
     if ((ndim != 2 && ndim != 3) || !h || !dt) return fail(SW_ERR_ARG, "bad arguments");
-    if (space_order < 2 || space_order > 16 || space_order % 2)
-        return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..16");
+    if (space_order < 2 || space_order > 20 || space_order % 2)
+        return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..20");
     if (!(cmax > 0.0)) return fail(SW_ERR_ARG, "cmax must be positive");
     const double a = a1d(space_order);
     double s = 0.0;
@@ -578,13 +578,6 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
     float *K = at<float>(ws, p->ws.model_k);
     float *aux = (p->prob.scheme != SW_CONST) ? at<float>(ws, p->ws.model_aux) : nullptr;
     SW_HIP(launch_model_prep(g, p->bcm, p->hz, p->hx, p->pad[0], p->prob.scheme, p->prob.dt, vel, rho, K, aux, s));
-    if (p->prob.scheme == SW_VD_STAGGERED) {
-        StencilParams F;
-        fill_params(p, ws, F);
-        SW_HIP(launch_face_buoyancy(g, p->bcm, p->hz, p->hx, p->pad[0], p->r, F.mj, aux,
-                                    const_cast<float *>(F.face[0]), const_cast<float *>(F.face[1]),
-                                    const_cast<float *>(F.face[2]), s));
-    }
     SW_HIP(hipMemcpyAsync(at<char>(ws, p->ws.damp), p->damp.data(), p->damp.size() * sizeof(float),
                           hipMemcpyHostToDevice, s));
     st = upload_points(p, p->src, p->ws.src, ws, s);
@@ -698,9 +691,8 @@ static sw_status enqueue_forward(sw_plan *p, const sw_fwd_io *io, hipStream_t s)
     return SW_OK;
 }
 
-sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
+static sw_status forward_impl(sw_plan *p, const sw_fwd_io *io, void *stream)
 {
-    set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
     sw_status st = check_prepared(p, io->workspace);
     if (st != SW_OK) return st;
@@ -759,6 +751,30 @@ sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
         p->graph_key = key;
     }
     SW_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(p->graph_exec), s));
+    return SW_OK;
+}
+
+sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
+{
+    set_error("");
+    sw_status st = forward_impl(p, io, stream);
+    if (st != SW_OK || !io->check_finite) return st;
+    // optional check: non-finite trace samples of the steps run and final field values
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *cnt = at<uint32_t>(io->workspace, p->ws.counter);
+    uint32_t bad[2] = {0u, 0u};
+    if (p->rec.count && io->nsteps_run) {
+        SW_HIP(launch_count_nonfinite(io->traces + int64_t(io->step0) * p->rec.count,
+                                      int64_t(io->nsteps_run) * p->rec.count, cnt, s));
+        SW_HIP(hipMemcpyAsync(&bad[0], cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SW_HIP(hipStreamSynchronize(s));
+    }
+    SW_HIP(launch_count_nonfinite(io->field[io->nsteps_run % 2], p->field_elems, cnt, s));
+    SW_HIP(hipMemcpyAsync(&bad[1], cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SW_HIP(hipStreamSynchronize(s));
+    if (bad[0] || bad[1])
+        return fail(SW_ERR_NONFINITE, std::to_string(bad[0]) + " non-finite trace samples and " +
+                                          std::to_string(bad[1]) + " non-finite wavefield values");
     return SW_OK;
 }
 

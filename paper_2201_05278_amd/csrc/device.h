@@ -40,7 +40,6 @@ struct StencilParams {
     const float *cur;       // p^n
     const float *K;         // multiplier of (L p): dt^2 c^2, or dt^2 rho c^2
     const float *aux;       // b = 1/rho (staggered) or rho (centred); unused otherwise
-    const float *face[3];   // staggered: face buoyancy b_{k+1/2} along z, x, y (stored at node k)
     const float2 *damp;     // (A, B) by squared layer distance
     int ndamp;              // entries of damp
     float *store;           // MODE_STORE: K (L p) written; MODE_IMAGE: read
@@ -48,9 +47,9 @@ struct StencilParams {
     float *ustore;          // MODE_STORE, staggered scheme: p^n written (the level imaged by the face term)
     Geom g;
     float c0;               // sum over axes of v_0 / h^2
-    float cz[9], cx[9], cy[9];     // second-derivative v_j / h^2 per axis
-    float sz[9], sx[9], sy[9];     // staggered s_j / h, or centred c_j / h (first derivative)
-    float mj[9];            // midpoint interpolation weights
+    float cz[11], cx[11], cy[11];  // second-derivative v_j / h^2 per axis (j <= R <= 10)
+    float sz[11], sx[11], sy[11];  // staggered s_j / h, or centred c_j / h (first derivative)
+    float mj[11];           // midpoint interpolation weights
     int ntx, nty, nzc, zc;  // tiling: tiles along x, y; z chunks and chunk length
     int bcm[3][2];          // ghost condition per internal axis (z, x, y) and side: 0 zero, 1 Dirichlet, 2 Neumann
     int gh;                 // ghost layers held in the stored halo (mirror sides)
@@ -173,6 +172,8 @@ hipError_t launch_record_batch(const ShotPoints *shots, int nshots, int max_coun
                                int step, int parity, hipStream_t s);
 
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+// *count = number of non-finite values among a[0 .. n) (count cleared first).
+hipError_t launch_count_nonfinite(const float *a, int64_t n, uint32_t *count, hipStream_t s);
 // Mirror ghosts of a wavefield: for every side with a Dirichlet (odd) or
 // Neumann (even) condition, ghost layer k = 1..depth takes +-p at the node k
 // inside the boundary node, along z, then x, then y.
@@ -184,12 +185,6 @@ hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_model_prep(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int scheme,
                              double dt, const float *vel, const float *rho, float *K, float *aux,
                              hipStream_t s);
-// Staggered scheme: face buoyancies b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1})
-// along each axis (b at the model node: mirror image across mirrored sides,
-// nearest grid node elsewhere), at every padded position.
-hipError_t launch_face_buoyancy(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int r,
-                                const float *mj, const float *b, float *fz, float *fx, float *fy,
-                                hipStream_t s);
 // rho_inj (or NULL) scales the injection multiplier to dt^2 rho c^2; rho_rec
 // (or NULL) divides the recording weights by rho (see k_point_coef).
 hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel, const float *rho_inj,

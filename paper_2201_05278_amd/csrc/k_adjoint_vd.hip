@@ -23,11 +23,11 @@ namespace {
 constexpr int kBlock = 256;
 
 struct AxisCoef {
-    float s[9];     // s_j / h along the axis
+    float s[11];    // s_j / h along the axis
 };
 
 struct MidCoef {
-    float m[9];     // midpoint interpolation weights m_j
+    float m[11];    // midpoint interpolation weights m_j
 };
 
 int grid_blocks(int64_t n)
@@ -76,7 +76,7 @@ __global__ void k_face_image_outer(Geom g, int axis, int r, AxisCoef c, const fl
 
 struct FaceTileParams {
     Geom g;
-    float sz[9], sx[9], sy[9];      // s_j / h per axis
+    float sz[11], sx[11], sy[11];   // s_j / h per axis
     const float *phi[2], *u[2];     // level pairs, accumulated in this order
     float *F[3];
     int ntx, nty, nzc, zc;
@@ -296,7 +296,7 @@ __global__ void k_vd_chain(Geom g, int r, int ndim, MidCoef c, const float *__re
 hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const *sj, int np,
                              const float *const *phi, const float *const *u, float *const *F, hipStream_t s)
 {
-    if (r < 1 || r > 8 || np < 1 || np > 2) return hipErrorInvalidValue;
+    if (r < 1 || r > 10 || np < 1 || np > 2) return hipErrorInvalidValue;
     // faces of the grid nodes: z-marching tiles
     FaceTileParams T{};
     T.g = g;
@@ -323,7 +323,9 @@ hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const 
     case 5: launch_face_tile<5>(ndim, np, T, s); break;
     case 6: launch_face_tile<6>(ndim, np, T, s); break;
     case 7: launch_face_tile<7>(ndim, np, T, s); break;
-    default: launch_face_tile<8>(ndim, np, T, s); break;
+    case 8: launch_face_tile<8>(ndim, np, T, s); break;
+    case 9: launch_face_tile<9>(ndim, np, T, s); break;
+    default: launch_face_tile<10>(ndim, np, T, s); break;
     }
     // faces no grid node owns (m < 0 or m >= n along each axis), pair by pair
     const int n[3] = {g.Z, g.X, g.Y};

@@ -27,6 +27,12 @@ hipError_t launch_vd_r7(int, int, int, const Tiling &, StencilParams &, hipStrea
 hipError_t launch_const_r8(int, int, const Tiling &, StencilParams &, hipStream_t);
 hipError_t launch_batch_r8(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
 hipError_t launch_vd_r8(int, int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_const_r9(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_batch_r9(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
+hipError_t launch_vd_r9(int, int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_const_r10(int, int, const Tiling &, StencilParams &, hipStream_t);
+hipError_t launch_batch_r10(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
+hipError_t launch_vd_r10(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 
 hipError_t launch_tb_r1(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
 hipError_t launch_tb_r2(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
@@ -48,6 +54,8 @@ hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParam
     case 6: return launch_const_r6(ndim, mode, t, P, s);
     case 7: return launch_const_r7(ndim, mode, t, P, s);
     case 8: return launch_const_r8(ndim, mode, t, P, s);
+    case 9: return launch_const_r9(ndim, mode, t, P, s);
+    case 10: return launch_const_r10(ndim, mode, t, P, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -64,6 +72,8 @@ hipError_t launch_const_batch(int r, int ndim, const Tiling &t, const StencilPar
     case 6: return launch_batch_r6(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
     case 7: return launch_batch_r7(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
     case 8: return launch_batch_r8(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+    case 9: return launch_batch_r9(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
+    case 10: return launch_batch_r10(ndim, t, shots, tile_start, nshots, parity, nblocks, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -94,6 +104,8 @@ hipError_t launch_vd(int scheme, int mode, int r, int ndim, const Tiling &t, Ste
     case 6: return launch_vd_r6(scheme, mode, ndim, t, P, s);
     case 7: return launch_vd_r7(scheme, mode, ndim, t, P, s);
     case 8: return launch_vd_r8(scheme, mode, ndim, t, P, s);
+    case 9: return launch_vd_r9(scheme, mode, ndim, t, P, s);
+    case 10: return launch_vd_r10(scheme, mode, ndim, t, P, s);
     default: return hipErrorInvalidValue;
     }
 }

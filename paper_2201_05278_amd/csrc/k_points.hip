@@ -10,6 +10,7 @@
 
 namespace sw {
 
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -33,6 +34,20 @@ __global__ void k_fill(float *__restrict__ p, int64_t n, float v)
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x)
         p[i] = v;
+}
+
+__global__ void k_zero_u32(uint32_t *c) { *c = 0u; }
+
+// One atomic per wavefront: each lane counts its non-finite values, the wave
+// sums its lanes, lane 0 adds the sum.
+__global__ void k_count_nonfinite(const float *__restrict__ a, int64_t n, uint32_t *__restrict__ count)
+{
+    uint32_t c = 0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        c += isfinite(a[i]) ? 0u : 1u;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
 
 __global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64_t n)
@@ -109,45 +124,6 @@ __global__ void k_ghost_axis(Geom g, int axis, int lo, int hi, int depth, float 
         if (src[axis] < 0 || src[axis] >= n[axis]) continue;   // extent below the ghost depth
         const float v = f[elem(g, src[0], src[1], src[2])];
         f[elem(g, dst[0], dst[1], dst[2])] = bc == 1 ? -v : v;
-    }
-}
-
-// Face buoyancies of the staggered operator at every padded position
-// (z, x, y): b_{k+1/2} = sum_j m_j (b_{k+j} + b_{k-j+1}) along each axis, with
-// b read at the model node of the extended grid (mirror image on mirrored
-// sides, else the nearest node).  The sum runs j = 1..R with fused
-// multiply-adds in that order.
-struct FaceCoef {
-    float m[9];
-};
-
-__global__ void k_face_buoyancy(Geom g, Sides sd, int hz, int hx, int pz, int r, FaceCoef c,
-                                const float *__restrict__ b, float *__restrict__ fz,
-                                float *__restrict__ fx, float *__restrict__ fy)
-{
-    const int64_t total = int64_t(pz) * g.px * g.py;
-    auto at = [&](int z, int x, int y) -> float {
-        z = model_axis(z, g.Z, sd.m[0][0], sd.m[0][1]);
-        x = model_axis(x, g.X, sd.m[1][0], sd.m[1][1]);
-        y = model_axis(y, g.Y, sd.m[2][0], sd.m[2][1]);
-        return b[g.origin + (int64_t(z) * g.px + x) * g.py + y];
-    };
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const int yy = int(i % g.py);
-        const int64_t t = i / g.py;
-        const int xx = int(t % g.px);
-        const int zz = int(t / g.px);
-        const int z = zz - hz, x = xx - hx, y = yy - 64;
-        float bz = 0.0f, bx = 0.0f, by = 0.0f;
-        for (int l = 1; l <= r; ++l) {
-            bz = fmaf(c.m[l], at(z + l, x, y) + at(z - l + 1, x, y), bz);
-            if (fx) bx = fmaf(c.m[l], at(z, x + l, y) + at(z, x - l + 1, y), bx);
-            by = fmaf(c.m[l], at(z, x, y + l) + at(z, x, y - l + 1), by);
-        }
-        fz[i] = bz;
-        if (fx) fx[i] = bx;
-        fy[i] = by;
     }
 }
 
@@ -377,6 +353,14 @@ hipError_t launch_model_prep(const Geom &g, const int (*bcm)[2], int halo_z, int
     return hipGetLastError();
 }
 
+hipError_t launch_count_nonfinite(const float *a, int64_t n, uint32_t *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, count);
+    if (n > 0)
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, float *field, hipStream_t s)
 {
     const int n[3] = {g.Z, g.X, g.Y};
@@ -390,19 +374,6 @@ hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, floa
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-hipError_t launch_face_buoyancy(const Geom &g, const int (*bcm)[2], int halo_z, int halo_x, int pz, int r,
-                                const float *mj, const float *b, float *fz, float *fx, float *fy,
-                                hipStream_t s)
-{
-    FaceCoef c{};
-    for (int l = 1; l <= r; ++l) c.m[l] = mj[l];
-    const int64_t total = int64_t(pz) * g.px * g.py;
-    hipLaunchKernelGGL(k_face_buoyancy, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, sides_of(bcm), halo_z,
-                       halo_x, pz,
-                       r, c, b, fz, fx, fy);
-    return hipGetLastError();
 }
 
 hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel, const float *rho_inj,

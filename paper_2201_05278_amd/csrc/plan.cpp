@@ -146,9 +146,8 @@ void build_workspace_map(sw_plan *p)
     const size_t fb = size_t(p->field_elems) * sizeof(float);
     w.model_k = take(fb);
     w.model_aux = (p->prob.scheme != SW_CONST) ? take(fb) : 0;
-    for (int a = 0; a < 3; ++a)
-        w.face[a] = (p->prob.scheme == SW_VD_STAGGERED && (a != 1 || p->ndim == 3)) ? take(fb) : 0;
     w.damp = take(size_t(p->damp_n) * 2 * sizeof(float));
+    w.counter = take(sizeof(uint32_t));
     auto pts = [&](const PointSet &ps, WorkspaceMap::Pts &o) {
         const size_t ne = std::max<size_t>(1, ps.node.size());
         const size_t nu = std::max<size_t>(1, ps.unode.size());

@@ -10,7 +10,7 @@
 
 namespace sw {
 
-constexpr int kMaxRadius = 8;      // space order 16
+constexpr int kMaxRadius = 10;     // space order 20
 constexpr int kRowAlign = 64;      // floats: interior rows start on 256-byte boundaries
 
 // Per-thread error message for sw_last_error().
@@ -43,8 +43,8 @@ struct PointSet {
 struct WorkspaceMap {
     size_t model_k = 0;      // float[field_elems]: K (dt^2 c^2, or dt^2 rho c^2)
     size_t model_aux = 0;    // float[field_elems]: b = 1/rho or rho (variable density)
-    size_t face[3] = {0, 0, 0};   // staggered: float[field_elems] face buoyancy b_{k+1/2} along z, x, y
     size_t damp = 0;         // float2[damp_n]: (A, B) by squared layer distance
+    size_t counter = 0;      // uint32: non-finite count of the optional finite check
     struct Pts {
         size_t ptr = 0, node = 0, pid = 0, d2 = 0, phys = 0, weight = 0;   // by point
         size_t unode = 0, uptr = 0, uent = 0;                     // by node

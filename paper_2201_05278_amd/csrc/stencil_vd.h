@@ -6,11 +6,13 @@
 //   (D+ q)_{k+1/2} = sum_j s_j (q_{k+j} - q_{k-j+1}) / h
 //   (D- F)_k       = sum_j s_j (F_{k+j-1/2} - F_{k-j+1/2}) / h
 //   b_{k+1/2}      = sum_j m_j (b_{k+j} + b_{k-j+1})
-// Fluxes along z are produced once per face as the march reaches it and kept
-// in a register queue (with register queues of p and b in front of the
-// node); fluxes along x are computed by each wave for its own rows from a
-// column of the LDS plane tile; fluxes along y are computed once per face into
-// LDS and differenced from there.  p and b planes are staged with a 2R halo.
+// Every face flux is formed once per face.  Along z the fluxes are produced as
+// the march reaches each face and kept in a register queue, fed by register
+// queues of p and b in front of the node; the x and y fluxes of the tile's
+// plane are formed once into LDS from LDS tiles of p and b (halo 2R - 1) and
+// differenced from there.  The face buoyancies are interpolated from b inside
+// the kernel, so the sweep streams p^n, p^{n-1}, K and b (20 bytes per node)
+// rather than three stored face arrays.
 //
 // Centred operator (paper, "Time discretization": expanded variable-density
 // equation), K = dt^2 c^2:
@@ -18,8 +20,11 @@
 // with the centred second and first derivatives; rho is staged like p (halo R)
 // with its own register queue along z.
 //
-// Model values outside the extended grid are read from the nearest grid node
-// (coordinates clamped), wavefield values outside it are zero.
+// Model values outside the extended grid are those of its model node (mirror
+// image across mirrored sides, nearest node elsewhere): the staggered kernel
+// reads b from the stored halo, which model preparation fills that way; the
+// centred kernel maps rho's coordinates itself.  Wavefield values outside it
+// are zero or mirror ghosts.
 #pragma once
 
 #include "device.h"
@@ -44,15 +49,32 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     constexpr int HXN = (NDIM == 3) ? (2 * HX + NW - 1) / NW : 0;   // x-halo rows per wave
     constexpr int YHN = (TX * 2 * H + NTH - 1) / NTH;               // y-halo items per thread
     constexpr int FXR = (NDIM == 3) ? FX : 0;     // x-face rows
-    // face items: rows of 64 (x faces, then the first 64 y faces of each tile
-    // row, wave aligned) and the last 2R - 1 y faces of each tile row
-    constexpr int NI = (FXR + TX) * 64 + TX * (2 * R - 1);
+    // face items: runs of MX consecutive x faces of one column (NRX runs per
+    // column: the 64 columns of a run index fill a wavefront), then runs of MY
+    // consecutive y faces of one tile row.  A run reads its p and b values once
+    // into registers (y runs with 16-byte LDS reads) and forms each face flux
+    // from them.
+    // (short runs: about 6 x faces, 4 y faces; longer runs that fit all items
+    // in one pass of the block's threads ran slower at 592^3: more registers,
+    // fewer resident waves)
+    constexpr int NRX = (NDIM == 3) ? (FXR + 5) / 6 : 0;
+    constexpr int MX = (NDIM == 3) ? (FXR + NRX - 1) / NRX : 1;
+    constexpr int MY = 4;
+    constexpr int NRY = (FY + MY - 1) / MY;
+    constexpr int NVY = (MY + 2 * R - 1 + 3) / 4 * 4;       // values a y run reads (float4 multiple)
+    constexpr int LYP = (NRY * MY + 2 * R - 1 + 3) / 4 * 4 > LY ? (NRY * MY + 2 * R - 1 + 3) / 4 * 4 : LY;
+    constexpr int SPR = NRX * MX + 2 * R - 1 > LX + 1 ? NRX * MX + 2 * R - 1 : LX + 1;
+    constexpr int NI = NRX * 64 + TX * NRY;
     constexpr int NIT = (NI + NTH - 1) / NTH;     // face items per thread
     constexpr int Q = 2 * R;                      // queue length (even: slots alternate)
     constexpr int kOut = 0x7ffffe00;
-    __shared__ float sp[LX + 1][LY];              // last row: sink for idle items
-    __shared__ float sfx[FX + 1][64];
-    __shared__ float sfy[TX + 1][FY];
+    // p and b of the plane (row LX: sink for idle halo items; rows past it are
+    // only read by the faces of the last x run beyond the tile's faces);
+    // 16-byte aligned rows for the y runs' vector reads
+    __shared__ __align__(16) float sp[SPR][LYP];
+    __shared__ __align__(16) float sb[SPR][LYP];
+    __shared__ float sfx[NRX * MX + 1][64];
+    __shared__ __align__(16) float sfy[TX + 1][NRY * MY];
 
     const Geom &g = P.g;
     const int lane = threadIdx.x & 63;
@@ -70,8 +92,9 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const int64_t sz = int64_t(g.px) * g.py;
     const bool yin = y < g.Y;
     const int ey = max(0, max(g.lo[2] - y, y - (g.lo[2] + g.np[2] - 1)));
-    // z window: planes zw .. zt - 1 (the queue reaches 2R - 1 planes ahead; planes
-    // off the grid lie in the stored halo and hold mirror ghosts or are masked)
+    // z window: planes zw .. zt - 1 (the queues reach 2R - 1 planes ahead; planes
+    // off the grid lie in the stored halo of 2R planes: wavefield planes there
+    // hold mirror ghosts or are masked, model planes hold the model's ghosts)
     const int zw = zb - 2 * R + 1;
     const int zt = ze + 2 * R - 1;
     const int pb = int(sz) * 4;
@@ -79,15 +102,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const int64_t w0 = g.base + int64_t(zw) * sz;
     const auto rc = buf_res(P.cur + w0, wbytes);
     const auto rn = buf_res(P.nxt + w0, wbytes);
-    // face buoyancies: planes fw .. fw + zc + 2R - 1 (faces zb - R .. ze + R - 2 along
-    // z; the padded halo of 2R planes holds those off the grid)
-    const int fw = zb - R;
-    const uint32_t fbytes = uint32_t(ze - zb + 2 * R) * uint32_t(pb);
-    const int64_t f0 = g.base + int64_t(fw) * sz;
-    const auto rfz = buf_res(P.face[0] + f0, fbytes);
-    const auto rfx = buf_res((NDIM == 3 ? P.face[1] : P.face[0]) + f0, fbytes);
-    const auto rfy = buf_res(P.face[2] + f0, fbytes);
-    auto fsoff = [&](int z) -> int { return (z - fw) * pb; };
+    const auto rb = buf_res(P.aux + w0, wbytes);
     const auto rk = buf_res(P.K + w0, wbytes);
     const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
     // imaging arrays share the wavefield layout and window
@@ -102,24 +117,24 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     auto keep = [](float v, unsigned m) -> float {
         return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m);
     };
-    // byte offsets in a plane: wavefield (zero off the grid); faces (inside the
-    // padded plane for faces -R .. n + R - 2 of every axis, out of range otherwise:
-    // those only feed nodes off the grid)
+    // byte offsets in a plane: wavefield (zero off the grid); wavefield reads
+    // (also mirror ghosts within the stored halo); model reads (the whole stored
+    // halo of 2R nodes, which feeds every face of the grid's nodes; positions
+    // beyond it only feed nodes off the grid and read zero)
     auto off = [&](int x, int yy) -> int {
         return (x >= 0 && x < g.X && yy >= 0 && yy < g.Y) ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
-    // wavefield reads: also mirror ghosts within the stored halo
     auto roff = [&](int x, int yy) -> int {
         const bool ok = axis_read(x, g.X, P.bcm[1][0], P.bcm[1][1], P.gh) &&
                         axis_read(yy, g.Y, P.bcm[2][0], P.bcm[2][1], P.gh);
         return ok ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
-    auto foff = [&](int x, int yy) -> int {
-        const bool ok = (NDIM == 2 || (x >= -R && x <= g.X + R - 2)) && yy >= -R && yy <= g.Y + R - 2;
+    auto moff = [&](int x, int yy) -> int {
+        const bool ok = (NDIM == 2 || (x >= -2 * R && x < g.X + 2 * R)) && yy >= -2 * R && yy < g.Y + 2 * R;
         return ok ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
 
-    int ro[RPT], rr[RPT], ex2[RPT];
+    int ro[RPT], rr[RPT], rm[RPT], ex2[RPT];
     bool rdir[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -127,21 +142,23 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const bool in = yin && x < g.X;
         ro[i] = off(x, y);
         rr[i] = roff(x, y);
+        rm[i] = moff(x, y);
         rdir[i] = axis_dirichlet(x, g.X, P.bcm[1][0], P.bcm[1][1]) ||
                   axis_dirichlet(y, g.Y, P.bcm[2][0], P.bcm[2][1]);
         const int ex = max(0, max(g.lo[1] - x, x - (g.lo[1] + g.np[1] - 1)));
         ex2[i] = in ? ex * ex + ey * ey : 0;
     }
-    int hxo[HXN > 0 ? HXN : 1], hxrow[HXN > 0 ? HXN : 1];
+    int hxo[HXN > 0 ? HXN : 1], hxm[HXN > 0 ? HXN : 1], hxrow[HXN > 0 ? HXN : 1];
 #pragma unroll
     for (int s = 0; s < HXN; ++s) {
         const int hr = wave + s * NW;
         const bool ok = hr < 2 * HX;
         const int x = (hr < HX) ? x0 - HX + hr : x0 + TX + hr - HX;
         hxo[s] = ok ? roff(x, y) : kOut;
+        hxm[s] = ok ? moff(x, y) : kOut;
         hxrow[s] = !ok ? LX : (hr < HX) ? hr : TX + hr;
     }
-    int hyo[YHN], hyrow[YHN], hycol[YHN];
+    int hyo[YHN], hym[YHN], hyrow[YHN], hycol[YHN];
 #pragma unroll
     for (int s = 0; s < YHN; ++s) {
         const int e = threadIdx.x + s * NTH;
@@ -150,35 +167,14 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const int yy = (c < H) ? y0 - H + c : y0 + 64 + c - H;
         const int x = x0 + row;
         hyo[s] = ok ? roff(x, yy) : kOut;
+        hym[s] = ok ? moff(x, yy) : kOut;
         hyrow[s] = ok ? HX + row : LX;
         hycol[s] = (c < H) ? c : 64 + c;
     }
-    // face items of phase two: kind 0 x face (row t, lane column), kind 1 y face
-    // (tile row r, face column c); idle items are y faces of the sink row with
-    // an out-of-range face offset.  The kind is uniform over a wavefront.
-    int fk[NIT], fa[NIT], fc[NIT], fo[NIT];
-#pragma unroll
-    for (int s = 0; s < NIT; ++s) {
-        const int e = threadIdx.x + s * NTH;
-        if (e < FXR * 64) {
-            fk[s] = 0; fa[s] = e / 64; fc[s] = e % 64;
-            fo[s] = foff(x0 - R + fa[s], y0 + fc[s]);
-        } else if (e < (FXR + TX) * 64) {
-            fk[s] = 1; fa[s] = e / 64 - FXR; fc[s] = e % 64;
-            fo[s] = foff(x0 + fa[s], y0 - R + fc[s]);
-        } else if (e < NI) {
-            const int t = e - (FXR + TX) * 64;
-            fk[s] = 1; fa[s] = t / (2 * R - 1); fc[s] = 64 + t % (2 * R - 1);
-            fo[s] = foff(x0 + fa[s], y0 - R + fc[s]);
-        } else {
-            fk[s] = 1; fa[s] = TX; fc[s] = 0; fo[s] = kOut;
-        }
-        fk[s] = __builtin_amdgcn_readfirstlane(fk[s]);
-    }
 
-    // queues, rotating with the unrolled step u: pq[(u + k) % Q] = p(z + k),
-    // fq[(u + k) % Q] = z flux at face (z - R + k) + 1/2
-    float pq[RPT][Q], fq[RPT][Q];
+    // queues, rotating with the unrolled step u: pq[(u + k) % Q] = p(z + k) and
+    // bq[(u + k) % Q] = b(z + k), fq[(u + k) % Q] = z flux at face (z - R + k) + 1/2
+    float pq[RPT][Q], bq[RPT][Q], fq[RPT][Q];
     const int zs = zb - 2 * R + 1;
 #pragma unroll
     for (int k = 0; k < 2 * R - 1; ++k) {
@@ -186,7 +182,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         const unsigned m = zmask(z);
         const int so = soff(z);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) pq[i][k] = keep(buf_ld<0>(rc, rr[i], so), m);
+        for (int i = 0; i < RPT; ++i) {
+            pq[i][k] = keep(buf_ld<0>(rc, rr[i], so), m);
+            bq[i][k] = buf_ld<0>(rb, rm[i], so);
+        }
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
@@ -194,28 +193,23 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         for (int k = 0; k < 2 * R; ++k) fq[i][k] = 0.0f;
 
     struct Slot {
-        float fp[RPT], fz[RPT], p[RPT], k[RPT];
+        float fp[RPT], fb[RPT], p[RPT], k[RPT];
         float2 ab[RPT];
-        float hxp[HXN > 0 ? HXN : 1], hyp[YHN], ff[NIT];
+        float hxp[HXN > 0 ? HXN : 1], hxb[HXN > 0 ? HXN : 1], hyp[YHN], hyb[YHN];
         float d[MODE == MODE_IMAGE ? RPT : 1], gr[MODE == MODE_IMAGE ? RPT : 1];
     };
-    // loads of plane z: the queue input at z + 2R - 1 and the z-face buoyancy at
-    // z + R - 1, and for z >= zb the plane's own p^{n-1}, K, (A, B), the halos
-    // of p and the x / y face buoyancies of the thread's face items
+    // loads of plane z: the queue inputs p and b at z + 2R - 1, and for z >= zb
+    // the plane's own p^{n-1}, K, (A, B) and the halos of p and b
     auto load = [&](int z, Slot &L) {
         const int zf = z + 2 * R - 1;
         const unsigned mf = zmask(zf);
-        const int sf = soff(zf), sfz = fsoff(z + R - 1);
+        const int sf = soff(zf);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             L.fp[i] = keep(buf_ld<0>(rc, rr[i], sf), mf);
-            L.fz[i] = buf_ld<NT>(rfz, ro[i], sfz);
+            L.fb[i] = buf_ld<0>(rb, rm[i], sf);
         }
         if (z < zb) return;
-        const int sff = fsoff(z);
-#pragma unroll
-        for (int s = 0; s < NIT; ++s)
-            L.ff[s] = (NDIM == 3 && fk[s] == 0) ? buf_ld<0>(rfx, fo[s], sff) : buf_ld<0>(rfy, fo[s], sff);
         const int so = soff(z);
         const int ez = max(0, max(g.lo[0] - z, z - (g.lo[0] + g.np[0] - 1)));
 #pragma unroll
@@ -229,9 +223,24 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
             }
         }
 #pragma unroll
-        for (int s = 0; s < HXN; ++s) L.hxp[s] = buf_ld<0>(rc, hxo[s], so);
+        for (int s = 0; s < HXN; ++s) {
+            L.hxp[s] = buf_ld<0>(rc, hxo[s], so);
+            L.hxb[s] = buf_ld<0>(rb, hxm[s], so);
+        }
 #pragma unroll
-        for (int s = 0; s < YHN; ++s) L.hyp[s] = buf_ld<0>(rc, hyo[s], so);
+        for (int s = 0; s < YHN; ++s) {
+            L.hyp[s] = buf_ld<0>(rc, hyo[s], so);
+            L.hyb[s] = buf_ld<0>(rb, hym[s], so);
+        }
+    };
+
+    // face buoyancy b_{m+1/2} = sum_l m_l (b_{m+l} + b_{m-l+1}), fused
+    // multiply-adds in the order l = 1 .. R, from values v(k) = b_{m+k}
+    auto bface = [&](auto v) -> float {
+        float acc = 0.0f;
+#pragma unroll
+        for (int l = 1; l <= R; ++l) acc = fmaf(P.mj[l], v(l) + v(1 - l), acc);
+        return acc;
     };
 
     Slot S[2];
@@ -244,7 +253,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         Slot &W = S[u % 2];
         if (z + 1 < ze) load(z + 1, S[(u + 1) % 2]);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) pq[i][(u + 2 * R - 1) % Q] = W.fp[i];
+        for (int i = 0; i < RPT; ++i) {
+            pq[i][(u + 2 * R - 1) % Q] = W.fp[i];
+            bq[i][(u + 2 * R - 1) % Q] = W.fb[i];
+        }
         // z flux at face (z + R - 1) + 1/2
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -252,33 +264,79 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
 #pragma unroll
             for (int l = 1; l <= R; ++l)
                 dp = fmaf(P.sz[l], pq[i][(u + R - 1 + l) % Q] - pq[i][(u + R - l) % Q], dp);
-            fq[i][(u + 2 * R - 1) % Q] = W.fz[i] * dp;
+            const float bf = bface([&](int k) { return bq[i][(u + R - 1 + k + Q) % Q]; });
+            fq[i][(u + 2 * R - 1) % Q] = bf * dp;
         }
 
         if (z >= zb) {
-            // phase one: stage p of plane z with an H-node halo
+            // phase one: stage p and b of plane z with an H-node halo
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) sp[HX + wave * RPT + i][H + lane] = pq[i][u % Q];
+            for (int i = 0; i < RPT; ++i) {
+                sp[HX + wave * RPT + i][H + lane] = pq[i][u % Q];
+                sb[HX + wave * RPT + i][H + lane] = bq[i][u % Q];
+            }
 #pragma unroll
-            for (int s = 0; s < HXN; ++s) sp[hxrow[s]][H + lane] = W.hxp[s];
+            for (int s = 0; s < HXN; ++s) {
+                sp[hxrow[s]][H + lane] = W.hxp[s];
+                sb[hxrow[s]][H + lane] = W.hxb[s];
+            }
 #pragma unroll
-            for (int s = 0; s < YHN; ++s) sp[hyrow[s]][hycol[s]] = W.hyp[s];
+            for (int s = 0; s < YHN; ++s) {
+                sp[hyrow[s]][hycol[s]] = W.hyp[s];
+                sb[hyrow[s]][hycol[s]] = W.hyb[s];
+            }
             __syncthreads();
 
-            // phase two: every x and y face flux of the tile, once
+            // phase two: every x and y face flux of the tile, once, by runs
 #pragma unroll
             for (int s = 0; s < NIT; ++s) {
-                float dp = 0.0f;
-                if (NDIM == 3 && fk[s] == 0) {
-                    const int t = fa[s], c = H + fc[s];
+                const int e = threadIdx.x + s * NTH;
+                if (NDIM == 3 && e < NRX * 64) {
+                    // x run: faces t0 .. t0 + MX - 1 of column c (face t lies
+                    // between rows x0 - R + t and x0 - R + t + 1; it reads LDS
+                    // rows t .. t + 2R - 1)
+                    const int c = e & 63, t0 = (e >> 6) * MX;
+                    float vp[MX + 2 * R - 1], vb[MX + 2 * R - 1];
 #pragma unroll
-                    for (int l = 1; l <= R; ++l) dp = fmaf(P.sx[l], sp[t + R - 1 + l][c] - sp[t + R - l][c], dp);
-                    sfx[t][fc[s]] = W.ff[s] * dp;
-                } else {
-                    const int r = HX + fa[s], c = fc[s];
+                    for (int j = 0; j < MX + 2 * R - 1; ++j) {
+                        vp[j] = sp[t0 + j][H + c];
+                        vb[j] = sb[t0 + j][H + c];
+                    }
 #pragma unroll
-                    for (int l = 1; l <= R; ++l) dp = fmaf(P.sy[l], sp[r][c + R - 1 + l] - sp[r][c + R - l], dp);
-                    sfy[fa[s]][fc[s]] = W.ff[s] * dp;
+                    for (int f = 0; f < MX; ++f) {
+                        float dp = 0.0f;
+#pragma unroll
+                        for (int l = 1; l <= R; ++l) dp = fmaf(P.sx[l], vp[f + R - 1 + l] - vp[f + R - l], dp);
+                        const float bf = bface([&](int k) { return vb[f + R - 1 + k]; });
+                        sfx[t0 + f][c] = bf * dp;
+                    }
+                } else if (e < NI) {
+                    // y run: faces c0 .. c0 + MY - 1 of tile row r (face c lies
+                    // between columns y0 - R + c and y0 - R + c + 1; it reads LDS
+                    // columns c .. c + 2R - 1)
+                    const int q = e - NRX * 64;
+                    const int r = q / NRY, c0 = (q % NRY) * MY;
+                    float vp[NVY], vb[NVY], out[MY];
+                    static_assert(MY % 4 == 0, "y runs store float4s");
+#pragma unroll
+                    for (int j = 0; j < NVY / 4; ++j) {
+                        const float4 a = *reinterpret_cast<const float4 *>(&sp[HX + r][c0 + 4 * j]);
+                        const float4 bb = *reinterpret_cast<const float4 *>(&sb[HX + r][c0 + 4 * j]);
+                        vp[4 * j] = a.x; vp[4 * j + 1] = a.y; vp[4 * j + 2] = a.z; vp[4 * j + 3] = a.w;
+                        vb[4 * j] = bb.x; vb[4 * j + 1] = bb.y; vb[4 * j + 2] = bb.z; vb[4 * j + 3] = bb.w;
+                    }
+#pragma unroll
+                    for (int f = 0; f < MY; ++f) {
+                        float dp = 0.0f;
+#pragma unroll
+                        for (int l = 1; l <= R; ++l) dp = fmaf(P.sy[l], vp[f + R - 1 + l] - vp[f + R - l], dp);
+                        const float bf = bface([&](int k) { return vb[f + R - 1 + k]; });
+                        out[f] = bf * dp;
+                    }
+#pragma unroll
+                    for (int j = 0; j < MY / 4; ++j)
+                        *reinterpret_cast<float4 *>(&sfy[r][c0 + 4 * j]) =
+                            make_float4(out[4 * j], out[4 * j + 1], out[4 * j + 2], out[4 * j + 3]);
                 }
             }
             __syncthreads();
@@ -537,7 +595,7 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
 }
 
 // Tile shapes (rows, waves) of the variable-density kernels in 3D; 2D uses (1, 1).
-#define SW_VD_SHAPES(X) X(16, 8) X(8, 8) X(8, 4) X(16, 4)
+#define SW_VD_SHAPES(X) X(16, 8) X(8, 8) X(8, 4) X(16, 4) X(16, 16)
 
 template <int R, int NDIM, int TX, int NW, int NT, int MODE>
 void launch_stag_mode(int occ, StencilParams &P, hipStream_t s)

@@ -236,8 +236,10 @@ class Propagator:
 
     # ---- propagation --------------------------------------------------------
     def forward(self, wavelet, saving_stride=0, checkpoint_every=0, use_graph=False, fields=None,
-                step0=0, nsteps_run=None, traces=None, stencil_ms=None):
-        """Run steps step0 .. step0+nsteps_run-1 (all by default).  stencil_ms: a
+                step0=0, nsteps_run=None, traces=None, stencil_ms=None, check_finite=False):
+        """Run steps step0 .. step0+nsteps_run-1 (all by default).  check_finite:
+        wait for the run and raise (SW_ERR_NONFINITE) if a trace sample written
+        or a value of the final wavefield is not finite.  stencil_ms: a
         host float32 numpy array of nsteps_run entries to receive each stencil
         launch's duration (the call then waits for the GPU)."""
         if self._vel is None:
@@ -274,6 +276,7 @@ class Propagator:
         io.step0 = int(step0)
         io.nsteps_run = nrun
         io.use_graph = 1 if use_graph else 0
+        io.check_finite = 1 if check_finite else 0
         if stencil_ms is not None:
             assert stencil_ms.dtype.name == "float32" and stencil_ms.size >= nrun
             io.stencil_ms = stencil_ms.ctypes.data_as(L.c_float_p)
@@ -381,6 +384,9 @@ class Batch:
         io = self._io(wavelets, n, use_graph)
         L.check("sw_batch_forward", L.lib().sw_batch_forward(self._batch, ctypes.byref(io), _stream()))
         self.current = n % 2
+        return self.traces
+
+
         return self.traces
 
 

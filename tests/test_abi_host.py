@@ -143,7 +143,7 @@ def _expect(status_name, fn, *a, **k):
 
 def test_invalid_problems_refused():
     _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 20), (1.0, 1.0), 3, 1e-3, 5)
-    _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 20), (1.0, 1.0), 18, 1e-3, 5)
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 20), (1.0, 1.0), 22, 1e-3, 5)
     _expect("SW_ERR_ARG", Propagator, (20, 20), (1.0, -1.0), 4, 1e-3, 5)
     _expect("SW_ERR_ARG", Propagator, (20, 20), (1.0, 1.0), 4, -1e-3, 5)
     # a padded z plane too large for the 32-bit window offsets (9000^2 x 4 B x 18 planes)

@@ -69,7 +69,8 @@ def _rel(a, b):
 @pytest.mark.parametrize("n,so,nsteps,nbl,every", [
     ((48, 57), 4, 90, 6, 16),      # 2D, segments of 16 with a partial last one
     ((48, 57), 8, 90, 6, 90),      # 2D, one segment
-    ((40, 37), 16, 60, 5, 7),      # 2D, the highest order
+    ((40, 37), 16, 60, 5, 7),      # 2D, order 16
+    ((44, 47), 20, 50, 5, 11),     # 2D, the highest order (20)
     ((26, 31, 70), 4, 50, 4, 13),  # 3D: several tiles along x and y, ragged
     ((26, 31, 70), 8, 50, 4, 50),
     ((22, 37, 70), 12, 40, 3, 9),  # 3D, long stencil (two rows per thread in the face pass)

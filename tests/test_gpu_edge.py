@@ -114,3 +114,27 @@ def test_single_plane_chunks_and_layerless_grid():
         torch.cuda.synchronize()
         assert torch.equal(r.traces, res.traces)
         assert torch.equal(prop.grid_view(r.fields[r.current]), prop.grid_view(res.fields[res.current]))
+
+
+def test_finite_check():
+    # a clean run passes the optional check; a wavelet holding an infinity makes
+    # the traces and the field non-finite and the call reports SW_ERR_NONFINITE
+    from paper_2201_05278_amd import SimwaveError
+    from paper_2201_05278_amd import _lib as L
+    n = (20, 24, 70)
+    vel = np.full(n, 2000.0, dtype=np.float32)
+    dt = 0.5 * oracle.coeffs.critical_dt((10.0,) * 3, 4, 2000.0)
+    prop = Propagator(n, (10.0,) * 3, 4, dt, 30, nbl=3)
+    prop.set_sources([[100.0, 120.0, 340.0]], "linear")
+    prop.set_receivers([[20.0, 120.0, 300.0], [150.0, 50.0, 600.0]], "linear")
+    prop.prepare(torch.from_numpy(vel).cuda())
+    wav = torch.from_numpy(oracle.ricker(15.0, dt, 30)[:, None].astype(np.float32)).cuda()
+    print("case: finite check, clean run", flush=True)
+    prop.forward(wav, check_finite=True)
+    bad = wav.clone()
+    bad[7, 0] = float("inf")
+    print("case: finite check, infinite wavelet sample", flush=True)
+    with pytest.raises(SimwaveError) as e:
+        prop.forward(bad, check_finite=True)
+    assert L.STATUS[e.value.status] == "SW_ERR_NONFINITE"
+    assert "non-finite" in str(e.value)

@@ -61,7 +61,7 @@ def test_homogeneous_2d_full_size():
     assert rel(field_np(prop, res), ref.p) < TOL
 
 
-@pytest.mark.parametrize("so", [2, 4, 8, 16])
+@pytest.mark.parametrize("so", [2, 4, 8, 16, 18, 20])
 def test_layered_3d_ragged_tiles(so):
     # extents that leave ragged tiles along every axis; off-grid Kaiser-sinc
     # source, on-grid and off-grid receivers

@@ -32,7 +32,7 @@ def test_vd_3d_ragged(scheme, so):
 
 
 @pytest.mark.parametrize("scheme", ["vd_staggered", "vd_centred"])
-@pytest.mark.parametrize("so", [4, 16])
+@pytest.mark.parametrize("so", [4, 16, 18, 20])
 def test_vd_2d(scheme, so):
     n = (70, 150)
     print(f"case: {scheme} 2D {n} SO{so}", flush=True)

@@ -19,7 +19,7 @@ import sympy as sp
 
 import oracle
 from oracle import coeffs
-from tests._analytic import (X, T, greens_2d, greens_3d, lambdify_space, grid_coords,
+from tests._analytic import (X, T, greens_2d, greens_3d, lambdify_space, grid_coords, exact_operators,
                              mms_forcing)
 
 
@@ -90,12 +90,28 @@ def _mms_run(scheme, so, h, c, u_expr, rho_expr, bc, L, tf, dt, receiver=None):
     coords = grid_coords(shape, (h, h))
     rho = lambdify_space(rho_expr, 2)(*coords)
     st = oracle.prepare(prob, np.full(shape, c), None if scheme == "const" else rho)
-    f_expr = mms_forcing(u_expr, rho_expr, c, 2)
-    f_fn = sp.lambdify((X[0], X[1], T), f_expr, "numpy")
     u_fn = sp.lambdify((X[0], X[1], T), u_expr, "numpy")
+    # u* = U(x) S(t) in every manufactured solution here: the forcing is then
+    # F1(x) S''(t) + F2(x) S(t) with F1 = U / c^2 and F2 = -(lap U - grad rho /
+    # rho . grad U), both evaluated on the grid once
+    space = [a for a in sp.Mul.make_args(u_expr) if not a.has(T)]
+    time_part = [a for a in sp.Mul.make_args(u_expr) if a.has(T)]
+    U, S = sp.Mul(*space), sp.Mul(*time_part)
+    if any(a.has(*X) for a in time_part):
+        f_fn = sp.lambdify((X[0], X[1], T), mms_forcing(u_expr, rho_expr, c, 2), "numpy")
 
-    def forcing(k):
-        return np.broadcast_to(f_fn(coords[0], coords[1], k * dt), shape)
+        def forcing(k):
+            return np.broadcast_to(f_fn(coords[0], coords[1], k * dt), shape)
+    else:
+        _, centred, _ = exact_operators(U, rho_expr, 2)
+        F1 = lambdify_space(U / c ** 2, 2)(*coords)
+        F2 = lambdify_space(-centred, 2)(*coords)
+        s0 = sp.lambdify(T, S, "math")
+        s2 = sp.lambdify(T, sp.diff(S, T, 2), "math")
+
+        def forcing(k):
+            t = k * dt
+            return F1 * s2(t) + F2 * s0(t)
 
     rec_pts = [receiver] if receiver is not None else []
     fw = oracle.forward(st, None, oracle.geometry_table(prob, [], role="source"),
