@@ -341,6 +341,20 @@ typedef struct sw_batch_io {
  * shots[s].field[nsteps_run % 2]. */
 sw_status sw_batch_forward(sw_batch *batch, const sw_batch_io *io, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run of
+ * sw_batch_forward with the batch's descriptor table held in a fixed device
+ * array owned by the library (1 MiB per GPU, about 1400 shots; kept until
+ * the process ends) instead of io->table, which is ignored.  Nothing is
+ * allocated: the array's address is resolved once per device, and the call
+ * enqueues the table upload and the launches on `stream` (io->use_graph must
+ * be 0: the caller may capture them in a graph of its own).  A batch whose
+ * table is larger than the array is refused (SW_ERR_UNSUPPORTED) before
+ * anything is enqueued.  Every call on one GPU shares the array: calls that
+ * overlap on the same GPU (other streams or threads) race on it and must be
+ * serialised by the caller.  Results are bitwise those of sw_batch_forward. */
+sw_status sw_batch_forward_static(sw_batch *batch, const sw_batch_io *io, void *stream);
+
 /* Pick the tile shape (rows per tile, waves per block), the z-chunk length,
  * cache policy and prefetch depth, for single plans also the two-step sweep
  * (when io->field2 is given) and a cap of 4 resident blocks per CU, and (for

@@ -101,6 +101,7 @@ SIGNATURES = {
     "sw_batch_destroy": (c_int32, [c_void_p]),
     "sw_batch_layout": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "sw_batch_forward": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), c_void_p]),
+    "sw_batch_forward_static": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), c_void_p]),
     "sw_plan_autotune": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), ctypes.c_char_p, c_void_p]),
     "sw_batch_autotune": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), ctypes.c_char_p, c_void_p]),
 }

@@ -330,6 +330,25 @@ sw_status sw_batch_forward(sw_batch *b, const sw_batch_io *io, void *stream)
     return SW_OK;
 }
 
+sw_status sw_batch_forward_static(sw_batch *b, const sw_batch_io *io, void *stream)
+{
+    set_error("");
+    if (!b || !io || !io->shots) return fail(SW_ERR_ARG, "NULL argument");
+    if (io->use_graph)
+        return fail(SW_ERR_ARG, "the no-allocation batch enqueues its launches without a graph of its own "
+                                "(instantiating one allocates); capture them in the caller's graph instead");
+    void *table = nullptr;
+    size_t cap = 0;
+    SW_HIP(static_batch_table(&table, &cap));
+    if (b->table_bytes > cap)
+        return fail(SW_ERR_UNSUPPORTED, "the batch's descriptor table takes " + std::to_string(b->table_bytes) +
+                                            " bytes, more than the fixed array of " + std::to_string(cap) +
+                                            " bytes: use sw_batch_forward with a caller-allocated table");
+    sw_batch_io run = *io;
+    run.table = table;
+    return sw_batch_forward(b, &run, stream);
+}
+
 sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_path, void *stream)
 {
     set_error("");

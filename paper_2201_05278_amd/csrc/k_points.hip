@@ -8,8 +8,38 @@
 // node or receiver and finish with a butterfly reduction inside the group.
 #include "device.h"
 
+#include <mutex>
+
 namespace sw {
 
+// Descriptor table of the batched forward's no-allocation variant
+// (sw_batch_forward_static): a fixed array in device memory, one copy per GPU
+// the library runs on, held until the process ends.  Host code never passes
+// the symbol itself to a kernel or a copy: static_batch_table resolves its
+// device address once per device.
+constexpr size_t kStaticTableBytes = size_t(1) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticTableBytes];
+
+hipError_t static_batch_table(void **ptr, size_t *bytes)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kStaticTableBytes;
+    return hipSuccess;
+}
 
 namespace {
 

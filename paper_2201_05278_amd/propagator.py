@@ -387,6 +387,16 @@ class Batch:
         return self.traces
 
 
+    def forward_static(self, wavelets, nsteps_run=None):
+        """The same run through the no-allocation entry point: the descriptor
+        table lives in the library's fixed device array (self.table unused);
+        launches are enqueued eagerly."""
+        n = self.props[0].nsteps if nsteps_run is None else nsteps_run
+        io = self._io(wavelets, n, False)
+        io.table = None
+        L.check("sw_batch_forward_static", L.lib().sw_batch_forward_static(self._batch, ctypes.byref(io),
+                                                                            _stream()))
+        self.current = n % 2
         return self.traces
 
 

@@ -31,8 +31,7 @@ def _shots(nshots, nsteps, seed):
     return props, wavs
 
 
-@pytest.mark.parametrize("nshots,nsteps,seed", [(5, 60, 4), (2, 35, 9)])
-def test_static_table_batch_matches_allocating_batch(nshots, nsteps, seed):
+def _check(nshots, nsteps, seed):
     props, wavs = _shots(nshots, nsteps, seed)
     batch = Batch(props)
     print(f"case: allocating batch, {nshots} shots, {nsteps} steps", flush=True)
@@ -51,7 +50,14 @@ def test_static_table_batch_matches_allocating_batch(nshots, nsteps, seed):
         assert torch.equal(p.grid_view(batch.fields[k][batch.current]), ref_fields[k]), k
 
 
-def test_static_table_refuses_graphs_and_oversized_tables():
+def test_static_table_batch_matches_allocating_batch_twice():
+    # two calls in a row on the shared array, the second with a smaller batch
+    # (fewer shots, fewer steps): the array keeps the first call's larger table
+    _check(5, 60, 4)
+    _check(2, 35, 9)
+
+
+def test_static_table_refuses_graphs():
     props, wavs = _shots(2, 10, 4)
     batch = Batch(props)
     io = batch._io(wavs, 10, True)
