@@ -149,64 +149,60 @@ def profile_pass(args):
     print("profile pass done: 5 steps of the 592^3 forward, 1 GiB copy", flush=True)
 
 
-# The paper's benchmark shapes ("Performance evaluation", Tables 2 and 3), its
-# times in seconds for the whole run (FP64, host-device transfers included)
-# on its fastest GPU back-end per order, for context only.
-PAPER_SHAPES = [
-    # name, physical n, h, layer per side, tf, c_max, [(order, steps, paper best s)]
-    ("marmousi2-shaped 2D", (351, 1701), 10.0, [(0, 70), (70, 70)], 2.0, 4700.0,
-     [(2, 1331, 0.36), (4, 1537, 0.43), (8, 1696, 0.47)]),
-    ("overthrust-shaped 3D", (207, 801, 801), 20.0, [(0, 0), (0, 0), (0, 0)], 4.0, 6000.0,
-     [(2, 2080, 28.30), (4, 2401, 40.36), (8, 2651, 63.12)]),
-]
+# The paper's benchmark shapes ("Performance evaluation", Tables 2 and 3) with
+# the boundary set-up of its examples, and its times in seconds for the whole
+# run (FP64, host-device transfers included) on its fastest GPU back-end per
+# order, for context only.
+PAPER_TIMES = {
+    "paper_shape_2d": [(2, 1331, 0.36), (4, 1537, 0.43), (8, 1696, 0.47)],
+    "paper_shape_3d": [(2, 2080, 28.30), (4, 2401, 40.36), (8, 2651, 63.12)],
+}
 
 
-def paper_shapes():
-    """Whole runs at the paper's grid shapes and step counts (dt at the
-    stability limit, as its counts imply), synthetic layered models reaching
-    its c_max, one source and 101 receivers; one JSON line per run."""
+def paper_shapes(dtypes=("float32", "float64")):
+    """Whole runs at the paper's grid shapes, boundary conditions and step
+    counts (dt at the stability limit, as its counts imply), synthetic layered
+    models reaching its c_max, one source and 101 receivers, in single and
+    double precision; one JSON line per run."""
     import torch
-    from paper_2201_05278_amd import Propagator, critical_dt, ricker
-    for name, n, h, nbl, tf, cmax, orders in PAPER_SHAPES:
-        rng = np.random.default_rng(7)
-        nd = len(n)
-        speeds = np.linspace(1500.0, cmax, 6)
-        vel = np.empty(n, dtype=np.float32)
-        edges = np.linspace(0, n[0], len(speeds) + 1).round().astype(int)
-        for k, v in enumerate(speeds):
-            vel[edges[k]:edges[k + 1]] = v
-        vel = np.minimum(vel + rng.normal(0.0, 20.0, n).astype(np.float32), cmax)
-        ext = [h * (k - 1) for k in n]
-        src = [[2 * h] + [e / 2 for e in ext[1:]]]
-        rec = [[h] + [e * (i / 100.0) for e in ext[1:2]] + ([ext[2] / 2] if nd == 3 else []) for i in range(101)]
-        for so, nt, paper_s in orders:
-            dt = critical_dt((h,) * nd, so, cmax)
-            prop = Propagator(n, (h,) * nd, so, dt, nt, nbl=[list(p) for p in nbl])
-            prop.set_sources(src, "linear")
-            prop.set_receivers(rec, "linear")
-            prop.prepare(torch.from_numpy(vel).cuda(), cmax=cmax)
-            wav = ricker(10.0, dt, nt).reshape(-1, 1).cuda()
-            if nd == 3:
-                # the library's own tiling search for this grid (2D runs are bound by
-                # launch latency, which its per-launch timing does not see)
-                prop.autotune()
-            fields = (prop.new_field(), prop.new_field())
-            traces = torch.zeros((nt, len(rec)), dtype=torch.float32, device="cuda")
-            # the whole time loop as one HIP graph: captured by the first call, replayed
-            prop.forward(wav, fields=fields, traces=traces, use_graph=True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            prop.forward(wav, fields=fields, traces=traces, use_graph=True)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            nodes = float(np.prod([k + a + b for k, (a, b) in zip(n, nbl)]))
-            print(json.dumps({"shape": name, "nodes": int(nodes), "space_order": so, "steps": nt,
-                              "seconds": round(el, 4), "gpts": round(nodes * nt / el / 1e9, 2),
-                              "paper_best_seconds": paper_s,
-                              "paper_best_gpts": round(nodes * nt / paper_s / 1e9, 3),
-                              "tiling": prop.tiling}), flush=True)
-            del prop
-            torch.cuda.empty_cache()
+    import workloads
+    from paper_2201_05278_amd import Propagator, critical_dt, steps_for, ricker
+    for name, make in (("paper_shape_2d", workloads.paper_shape_2d), ("paper_shape_3d", workloads.paper_shape_3d)):
+        for so, nt_paper, paper_s in PAPER_TIMES[name]:
+            wl = make(space_order=so)
+            cmax = wl.extra["cmax"]
+            dt = critical_dt(wl.h, so, cmax)
+            nt = steps_for(wl.extra["tf"], dt)
+            assert nt == nt_paper, (name, so, nt, nt_paper)
+            for dtype in dtypes:
+                tdt = torch.float64 if dtype == "float64" else torch.float32
+                prop = Propagator(wl.n, wl.h, so, dt, nt, nbl=[list(p) for p in wl.nbl],
+                                  bc=[list(b) for b in wl.bc], dtype=dtype)
+                prop.set_sources(wl.src, wl.src_interp)
+                prop.set_receivers(wl.rec, wl.rec_interp)
+                prop.prepare(torch.from_numpy(wl.vel).to(tdt).cuda(), cmax=cmax)
+                wav = ricker(wl.f_peak, dt, nt).reshape(-1, 1).to(tdt).cuda()
+                if wl.ndim == 3 and dtype == "float32":
+                    # the library's own tiling search for this grid (2D runs are bound by
+                    # launch latency, which its per-launch timing does not see)
+                    prop.autotune()
+                fields = (prop.new_field(), prop.new_field())
+                traces = torch.zeros((nt, len(wl.rec)), dtype=tdt, device="cuda")
+                graph = dtype == "float32"       # the single-precision loop as one HIP graph
+                prop.forward(wav, fields=fields, traces=traces, use_graph=graph)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                prop.forward(wav, fields=fields, traces=traces, use_graph=graph)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                nodes = float(np.prod([k + a + b for k, (a, b) in zip(wl.n, wl.nbl)]))
+                print(json.dumps({"shape": name, "dtype": dtype, "nodes": int(nodes), "space_order": so,
+                                  "steps": nt, "boundary": wl.bc, "seconds": round(el, 4),
+                                  "gpts": round(nodes * nt / el / 1e9, 2), "paper_best_seconds": paper_s,
+                                  "paper_best_gpts": round(nodes * nt / paper_s / 1e9, 3),
+                                  "tiling": prop.tiling}), flush=True)
+                del prop, fields, traces
+                torch.cuda.empty_cache()
 
 
 def cpu_baseline(wl, dt, steps):

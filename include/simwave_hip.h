@@ -80,6 +80,7 @@ enum { SW_CONST = 0, SW_VD_STAGGERED = 1, SW_VD_CENTRED = 2 };
 enum { SW_BC_NONE = 0, SW_BC_DIRICHLET = 1, SW_BC_NEUMANN = 2 };
 enum { SW_SRC = 0, SW_REC = 1 };
 enum { SW_INTERP_HICKS = 0, SW_INTERP_LINEAR = 1 };
+enum { SW_F32 = 0, SW_F64 = 1 };
 
 /* Problem description (paper: SpaceModel, config_boundary, TimeModel). */
 typedef struct sw_problem {
@@ -101,6 +102,10 @@ typedef struct sw_problem {
     double  damp_power;     /* p (paper default 3) */
     double  dt;             /* time step, seconds */
     int32_t nsteps;         /* number of time steps N */
+    int32_t dtype;          /* SW_F32 (0: single precision, every entry point) or SW_F64
+                               (double precision, as the paper's dtype option: constant
+                               density forward only, through sw_model_prepare_f64 and
+                               sw_forward_f64) */
 } sw_problem;
 
 /* Sizes of every caller-allocated buffer for a plan. */
@@ -232,6 +237,35 @@ typedef struct sw_fwd_io {
 } sw_fwd_io;
 
 sw_status sw_forward(sw_plan *plan, const sw_fwd_io *io, void *stream);
+
+/* ---- double precision (SW_F64 plans) ------------------------------------ */
+
+/* Model preparation of an SW_F64 plan: K = dt^2 c^2 in double precision from
+ * the device velocity vel_dev [physical_nodes] (double), the damping table and
+ * the point coefficients, into the workspace (sw_plan_layout's
+ * workspace_bytes, which counts 8-byte values for such a plan).  Errors as
+ * for sw_model_prepare; SW_ERR_STATE for a single-precision plan. */
+sw_status sw_model_prepare_f64(sw_plan *plan, const double *vel_dev, double cmax, void *workspace,
+                               void *stream);
+
+/* Buffers of the double-precision forward; meaning, sizes and ownership as in
+ * sw_fwd_io, with double elements. */
+typedef struct sw_fwd64_io {
+    void *workspace;          /* prepared by sw_model_prepare_f64 */
+    const double *wavelet;    /* device [nsteps][nsrc] */
+    double *field[2];         /* device, field_elems doubles each (as sw_fwd_io) */
+    double *traces;           /* device [nsteps][nrec] */
+    double *snaps;            /* device [nsteps / saving_stride][grid_nodes] or NULL */
+    int32_t saving_stride;
+    int32_t step0;
+    int32_t nsteps_run;
+} sw_fwd64_io;
+
+/* The forward of an SW_F64 plan (paper, "Time discretization" update with the
+ * damped source term), stencil, injection, recording and mirror ghosts in
+ * double precision; the same steps and outputs as sw_forward (no checkpoints,
+ * graphs, two-step sweeps or timing).  Enqueue only. */
+sw_status sw_forward_f64(sw_plan *plan, const sw_fwd64_io *io, void *stream);
 
 /* ---- adjoint and velocity gradient -------------------------------------- */
 

@@ -40,7 +40,7 @@ class Problem(ctypes.Structure):
                 ("space_order", c_int32), ("scheme", c_int32),
                 ("nbl", (c_int32 * 2) * 3), ("bc", (c_int32 * 2) * 3),
                 ("damp_alpha", c_double), ("damp_power", c_double), ("dt", c_double),
-                ("nsteps", c_int32)]
+                ("nsteps", c_int32), ("dtype", c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -56,6 +56,12 @@ class FwdIO(ctypes.Structure):
                 ("ckpt", c_void_p), ("ckpt_every", c_int32), ("step0", c_int32),
                 ("nsteps_run", c_int32), ("use_graph", c_int32), ("stencil_ms", c_float_p),
                 ("field2", c_void_p * 2), ("check_finite", c_int32)]
+
+
+class Fwd64IO(ctypes.Structure):
+    _fields_ = [("workspace", c_void_p), ("wavelet", c_void_p), ("field", c_void_p * 2),
+                ("traces", c_void_p), ("snaps", c_void_p), ("saving_stride", c_int32),
+                ("step0", c_int32), ("nsteps_run", c_int32)]
 
 
 class AdjIO(ctypes.Structure):
@@ -94,6 +100,8 @@ SIGNATURES = {
                                  ctypes.POINTER(c_int64), ctypes.POINTER(c_int32), c_float_p]),
     "sw_model_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "sw_forward": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), c_void_p]),
+    "sw_model_prepare_f64": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
+    "sw_forward_f64": (c_int32, [c_void_p, ctypes.POINTER(Fwd64IO), c_void_p]),
     "sw_adjoint": (c_int32, [c_void_p, ctypes.POINTER(AdjIO), c_void_p]),
     "sw_plan_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
     "sw_plan_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
+#include "device64.h"
 
 namespace sw {
 const std::string &last_error();
@@ -131,6 +132,9 @@ Tiling choose_tiling(const sw_plan *p)
     if (p->ndim == 2) {
         t.tx = 1;
         t.nw = 1;
+    } else if (p->prob.dtype == SW_F64) {
+        t.tx = kTile64X;
+        t.nw = kTile64W;
     } else if (p->prob.scheme != SW_CONST) {
         // variable-density kernels: 8x4 staggered, 16x8 centred (tiling sweep, 592^3 SO8)
         const bool stag = p->prob.scheme == SW_VD_STAGGERED;
@@ -204,7 +208,7 @@ void set_tiles(const sw_plan *p, const Tiling &t, StencilParams &P)
 {
     const int cols = tile_cols(p, t.ts);
     // a z window (chunk plus 4R planes) stays below 2^31 bytes: 32-bit buffer offsets
-    const int64_t pbytes = int64_t(p->pad[1]) * p->pad[2] * 4;
+    const int64_t pbytes = int64_t(p->pad[1]) * p->pad[2] * (p->prob.dtype == SW_F64 ? 8 : 4);
     const int zmax = int(std::max<int64_t>(1, (int64_t(1) << 31) / pbytes - 4 * p->r - 2));
     P.ntx = (p->dims[1] + t.tx - 1) / t.tx;
     P.nty = (p->dims[2] + cols - 1) / cols;
@@ -274,6 +278,9 @@ sw_status check_problem(const sw_problem *q)
         return fail(SW_ERR_UNSUPPORTED, "space order must be even in 2..20");
     if (q->scheme != SW_CONST && q->scheme != SW_VD_STAGGERED && q->scheme != SW_VD_CENTRED)
         return fail(SW_ERR_ARG, "unknown scheme");
+    if (q->dtype != SW_F32 && q->dtype != SW_F64) return fail(SW_ERR_ARG, "dtype must be SW_F32 or SW_F64");
+    if (q->dtype == SW_F64 && q->scheme != SW_CONST)
+        return fail(SW_ERR_UNSUPPORTED, "double precision covers the constant-density scheme");
     const int r = q->space_order / 2;
     for (int i = 0; i < q->ndim; ++i) {
         if (q->n[i] < 1) return fail(SW_ERR_ARG, "grid extents must be >= 1");
@@ -400,7 +407,8 @@ sw_status sw_plan_create(const sw_problem *prob, sw_plan **out)
         }
     // stencil launches address a window of at most (4R + 2) z planes with
     // 32-bit byte offsets
-    if (int64_t(p->pad[1]) * p->pad[2] * 4 * (4 * p->r + 2) >= (int64_t(1) << 31)) {
+    const int64_t es = p->prob.dtype == SW_F64 ? 8 : 4;
+    if (int64_t(p->pad[1]) * p->pad[2] * es * (4 * p->r + 2) >= (int64_t(1) << 31)) {
         delete p;
         return fail(SW_ERR_UNSUPPORTED, "a z plane of the padded grid is too large for 32-bit window offsets "
                                         "(plane bytes x (4R + 2) must stay below 2^31)");
@@ -413,6 +421,8 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
 {
     set_error("");
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
+    if (p->prob.dtype == SW_F64 && t)
+        return fail(SW_ERR_UNSUPPORTED, "double-precision plans use their fixed tile shape");
     sw_tiling d{0, 0, 0, -1, 0, 0, 0, -1};
     if (t) d = *t;
     if (d.zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
@@ -563,6 +573,7 @@ sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, doubl
 {
     set_error("");
     if (!p || !vel || !ws) return fail(SW_ERR_ARG, "NULL argument");
+    if (p->prob.dtype == SW_F64) return fail(SW_ERR_STATE, "a double-precision plan is prepared by sw_model_prepare_f64");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SW_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (p->prob.scheme != SW_CONST && !rho) return fail(SW_ERR_ARG, "variable density needs rho");
     if (!(cmax > 0.0)) return fail(SW_ERR_ARG, "cmax must be positive");
@@ -694,6 +705,7 @@ static sw_status enqueue_forward(sw_plan *p, const sw_fwd_io *io, hipStream_t s)
 static sw_status forward_impl(sw_plan *p, const sw_fwd_io *io, void *stream)
 {
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
+    if (p->prob.dtype == SW_F64) return fail(SW_ERR_STATE, "a double-precision plan runs by sw_forward_f64");
     sw_status st = check_prepared(p, io->workspace);
     if (st != SW_OK) return st;
     if (!io->field[0] || !io->field[1] || io->field[0] == io->field[1])
@@ -784,6 +796,7 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
     if (p->prob.scheme == SW_VD_CENTRED)
         return fail(SW_ERR_UNSUPPORTED, "the adjoint covers the constant-density and staggered schemes");
+    if (p->prob.dtype == SW_F64) return fail(SW_ERR_UNSUPPORTED, "the adjoint runs in single precision");
     if (p->mirror)
         return fail(SW_ERR_UNSUPPORTED, "the adjoint covers zero ghosts (no Dirichlet / Neumann sides)");
     sw_status st = check_prepared(p, io->workspace);

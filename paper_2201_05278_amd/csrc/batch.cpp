@@ -232,6 +232,7 @@ sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out)
         if (p->prob.scheme != SW_CONST)
             return fail(SW_ERR_UNSUPPORTED, "batches cover the constant-density scheme");
         if (p->mirror) return fail(SW_ERR_UNSUPPORTED, "batches cover zero ghosts (no Dirichlet / Neumann sides)");
+        if (p->prob.dtype == SW_F64) return fail(SW_ERR_UNSUPPORTED, "batches run in single precision");
         if (p->ndim != p0->ndim || p->r != p0->r || p->prob.nsteps != p0->prob.nsteps)
             return fail(SW_ERR_ARG, "all shots need the same ndim, space order and step count");
     }
@@ -353,6 +354,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
 {
     set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
+    if (p->prob.dtype == SW_F64) return fail(SW_ERR_UNSUPPORTED, "double-precision plans use their fixed tile shape");
     sw_status st = check_prepared(p, io->workspace);
     if (st != SW_OK) return st;
     if (!io->field[0] || !io->field[1] || io->field[0] == io->field[1])

@@ -35,25 +35,34 @@ __device__ inline int xcd_remap(int bid, int n)
     return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
 }
 
-struct StencilParams {
-    float *nxt;             // p^{n-1} on entry, p^{n+1} on exit (in place)
-    const float *cur;       // p^n
-    const float *K;         // multiplier of (L p): dt^2 c^2, or dt^2 rho c^2
-    const float *aux;       // b = 1/rho (staggered) or rho (centred); unused otherwise
-    const float2 *damp;     // (A, B) by squared layer distance
+// Pair type of a value type: the (A, B) damping entries.
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
+// Parameters of one stencil launch over values of type T (float, or double
+// for the double-precision forward).
+template <typename T>
+struct StencilParamsT {
+    T *nxt;                 // p^{n-1} on entry, p^{n+1} on exit (in place)
+    const T *cur;           // p^n
+    const T *K;             // multiplier of (L p): dt^2 c^2, or dt^2 rho c^2
+    const T *aux;           // b = 1/rho (staggered) or rho (centred); unused otherwise
+    const typename Pair<T>::type *damp;   // (A, B) by squared layer distance
     int ndamp;              // entries of damp
-    float *store;           // MODE_STORE: K (L p) written; MODE_IMAGE: read
-    float *grad;            // MODE_IMAGE: += p * store / K^2
-    float *ustore;          // MODE_STORE, staggered scheme: p^n written (the level imaged by the face term)
+    T *store;               // MODE_STORE: K (L p) written; MODE_IMAGE: read
+    T *grad;                // MODE_IMAGE: += p * store / K^2
+    T *ustore;              // MODE_STORE, staggered scheme: p^n written (the level imaged by the face term)
     Geom g;
-    float c0;               // sum over axes of v_0 / h^2
-    float cz[11], cx[11], cy[11];  // second-derivative v_j / h^2 per axis (j <= R <= 10)
-    float sz[11], sx[11], sy[11];  // staggered s_j / h, or centred c_j / h (first derivative)
-    float mj[11];           // midpoint interpolation weights
+    T c0;                   // sum over axes of v_0 / h^2
+    T cz[11], cx[11], cy[11];   // second-derivative v_j / h^2 per axis (j <= R <= 10)
+    T sz[11], sx[11], sy[11];   // staggered s_j / h, or centred c_j / h (first derivative)
+    T mj[11];               // midpoint interpolation weights
     int ntx, nty, nzc, zc;  // tiling: tiles along x, y; z chunks and chunk length
     int bcm[3][2];          // ghost condition per internal axis (z, x, y) and side: 0 zero, 1 Dirichlet, 2 Neumann
     int gh;                 // ghost layers held in the stored halo (mirror sides)
 };
+using StencilParams = StencilParamsT<float>;
 
 // Whether the wavefield at coordinate v of an axis of extent n is read from
 // memory: grid nodes, and ghost nodes within the stored halo on a side with a

@@ -1,0 +1,264 @@
+// Double-precision instance of the constant-density forward (the precision
+// of the paper's benchmark runs): model preparation, point coefficients,
+// injection, recording, mirror ghosts, snapshots, and the block-tile stencil
+// (the same tile code as single precision, instantiated for double with one
+// tile shape per dimension).
+#include "stencil_const.h"
+
+#include "device64.h"
+
+namespace sw {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+int blocks_for64(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return int(b);
+}
+
+__global__ void k_fill64(double *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0.0;
+}
+
+// K = dt^2 c^2 at every padded position, from the model node of its
+// coordinates (mirror image across mirrored sides, nearest node elsewhere).
+__global__ void k_prep64(Geom g, int m0, int m1, int m2, int m3, int m4, int m5, int hz, int hx, int pz,
+                         double dt2, const double *__restrict__ vel, double *__restrict__ K)
+{
+    const int64_t total = int64_t(pz) * g.px * g.py;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int yy = int(i % g.py);
+        const int64_t t = i / g.py;
+        const int xx = int(t % g.px);
+        const int zz = int(t / g.px);
+        const int z = model_axis(zz - hz, g.Z, m0, m1);
+        const int x = model_axis(xx - hx, g.X, m2, m3);
+        const int y = model_axis(yy - 64, g.Y, m4, m5);
+        const int pzc = min(max(z - g.lo[0], 0), g.np[0] - 1);
+        const int pxc = min(max(x - g.lo[1], 0), g.np[1] - 1);
+        const int pyc = min(max(y - g.lo[2], 0), g.np[2] - 1);
+        const double c = vel[(int64_t(pzc) * g.np[1] + pxc) * g.np[2] + pyc];
+        K[i] = dt2 * c * c;
+    }
+}
+
+// Injection coefficient A(node) dt^2 c^2 w / dV and recording weight w (the
+// weight times `scale`, 1 / dV for sources).
+__global__ void k_point_coef64(PointTable64 t, const double2 *__restrict__ damp, const double *__restrict__ vel,
+                               double dt, double scale)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= t.nent) return;
+    const double c = vel[t.phys[e]];
+    const double w = t.weight[e] * scale;
+    t.coef_a[e] = damp[t.d2[e]].x * (dt * dt * c * c) * w;
+    t.wscaled[e] = w;
+}
+
+template <int G>
+__device__ inline double group_sum64(double v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+// Deterministic gather per unique node, as the single-precision injection.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_inject64(PointTable64 t, double *__restrict__ field,
+                                                     const double *__restrict__ amp)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = gid / G, sub = gid % G;
+    double sa = 0.0;
+    if (u < t.nuniq)
+        for (int k = t.uptr[u] + sub; k < t.uptr[u + 1]; k += G) {
+            const int e = t.uent[k];
+            sa = fma(t.coef_a[e], amp[t.pid[e]], sa);
+        }
+    sa = group_sum64<G>(sa);
+    if (u < t.nuniq && sub == 0) field[t.unode[u]] += sa;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_record64(PointTable64 t, const double *__restrict__ field,
+                                                     double *__restrict__ out)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pt = gid / G, sub = gid % G;
+    double acc = 0.0;
+    if (pt < t.count)
+        for (int e = t.ptr[pt] + sub; e < t.ptr[pt + 1]; e += G) acc += t.wscaled[e] * field[t.node[e]];
+    acc = group_sum64<G>(acc);
+    if (pt < t.count && sub == 0) out[pt] = acc;
+}
+
+// Mirror ghosts along one axis (Dirichlet odd, Neumann even), as in single
+// precision.
+__global__ void k_ghost64(Geom g, int axis, int lo, int hi, int depth, double *__restrict__ f)
+{
+    const int n[3] = {g.Z, g.X, g.Y};
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    const int64_t rows = int64_t(n[a1]) * n[a2];
+    const int64_t total = rows * depth * 2;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = i % rows;
+        const int k = 1 + int((i / rows) % depth);
+        const int side = int(i / (rows * depth));
+        const int bc = side ? hi : lo;
+        if (bc == 0) continue;
+        int src[3] = {0, 0, 0}, dst[3] = {0, 0, 0};
+        src[a1] = dst[a1] = int(r / n[a2]);
+        src[a2] = dst[a2] = int(r % n[a2]);
+        if (side == 0) {
+            dst[axis] = -k;
+            src[axis] = k;
+        } else {
+            dst[axis] = n[axis] - 1 + k;
+            src[axis] = n[axis] - 1 - k;
+        }
+        if (src[axis] < 0 || src[axis] >= n[axis]) continue;
+        const double v = f[elem(g, src[0], src[1], src[2])];
+        f[elem(g, dst[0], dst[1], dst[2])] = bc == 1 ? -v : v;
+    }
+}
+
+__global__ void k_snapshot64(Geom g, const double *__restrict__ f, double *__restrict__ out)
+{
+    const int64_t total = int64_t(g.Z) * g.X * g.Y;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int y = int(i % g.Y);
+        const int64_t t = i / g.Y;
+        const int x = int(t % g.X);
+        const int z = int(t / g.X);
+        out[i] = f[elem(g, z, x, y)];
+    }
+}
+
+template <int R, int NDIM, int TX, int NW>
+__global__ void __launch_bounds__(64 * NW) k_const64(StencilParamsT<double> P)
+{
+    const_tile<double, R, NDIM, TX, NW, MODE_FWD, 1, 1>(P, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R>
+void launch_k_const64(int ndim, StencilParamsT<double> &P, hipStream_t s)
+{
+    const dim3 grid(P.ntx * P.nty * P.nzc);
+    if (ndim == 2) hipLaunchKernelGGL((k_const64<R, 2, 1, 1>), grid, dim3(64), 0, s, P);
+    else hipLaunchKernelGGL((k_const64<R, 3, kTile64X, kTile64W>), grid, dim3(64 * kTile64W), 0, s, P);
+}
+
+}  // namespace
+
+hipError_t launch_fill64(double *p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill64, dim3(blocks_for64(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep64(const Geom &g, const int (*bcm)[2], int hz, int hx, int pz, double dt, const double *vel,
+                         double *K, hipStream_t s)
+{
+    const int64_t total = int64_t(pz) * g.px * g.py;
+    hipLaunchKernelGGL(k_prep64, dim3(blocks_for64(total)), dim3(kBlock), 0, s, g, bcm[0][0] != 0, bcm[0][1] != 0,
+                       bcm[1][0] != 0, bcm[1][1] != 0, bcm[2][0] != 0, bcm[2][1] != 0, hz, hx, pz, dt * dt, vel, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_coef64(const PointTable64 &t, const double2 *damp, const double *vel, double dt,
+                               double scale, hipStream_t s)
+{
+    if (t.nent <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_point_coef64, dim3((t.nent + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t, damp, vel,
+                       dt, scale);
+    return hipGetLastError();
+}
+
+static int group_of(int n)
+{
+    int g = 1;
+    while (g < n && g < 64) g *= 2;
+    return g;
+}
+
+#define SW_G64(G, KERNEL, N, ...)                                                                          \
+    switch (G) {                                                                                           \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, dim3((int64_t(N) * 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, dim3((int64_t(N) * 2 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, dim3((int64_t(N) * 4 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, dim3((int64_t(N) * 8 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break;   \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, dim3((int64_t(N) * 16 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break; \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3((int64_t(N) * 32 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<64>, dim3((int64_t(N) * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, __VA_ARGS__); break; \
+    }
+
+hipError_t launch_inject64(const PointTable64 &t, double *field, const double *amp, hipStream_t s)
+{
+    if (t.nuniq <= 0) return hipSuccess;
+    const int G = group_of(t.max_per_node);
+    SW_G64(G, k_inject64, t.nuniq, s, t, field, amp);
+    return hipGetLastError();
+}
+
+hipError_t launch_record64(const PointTable64 &t, const double *field, double *out, hipStream_t s)
+{
+    if (t.count <= 0) return hipSuccess;
+    const int G = group_of(t.max_per_point);
+    SW_G64(G, k_record64, t.count, s, t, field, out);
+    return hipGetLastError();
+}
+
+#undef SW_G64
+
+hipError_t launch_ghost64(const Geom &g, const int (*bcm)[2], int depth, double *field, hipStream_t s)
+{
+    const int n[3] = {g.Z, g.X, g.Y};
+    for (int axis = 0; axis < 3; ++axis) {
+        if (!bcm[axis][0] && !bcm[axis][1]) continue;
+        const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+        const int64_t total = int64_t(n[a1]) * n[a2] * depth * 2;
+        hipLaunchKernelGGL(k_ghost64, dim3(blocks_for64(total)), dim3(kBlock), 0, s, g, axis, bcm[axis][0],
+                           bcm[axis][1], depth, field);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_snapshot64(const Geom &g, const double *field, double *out, hipStream_t s)
+{
+    const int64_t total = int64_t(g.Z) * g.X * g.Y;
+    hipLaunchKernelGGL(k_snapshot64, dim3(blocks_for64(total)), dim3(kBlock), 0, s, g, field, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_const64(int r, int ndim, StencilParamsT<double> &P, hipStream_t s)
+{
+    switch (r) {
+    case 1: launch_k_const64<1>(ndim, P, s); break;
+    case 2: launch_k_const64<2>(ndim, P, s); break;
+    case 3: launch_k_const64<3>(ndim, P, s); break;
+    case 4: launch_k_const64<4>(ndim, P, s); break;
+    case 5: launch_k_const64<5>(ndim, P, s); break;
+    case 6: launch_k_const64<6>(ndim, P, s); break;
+    case 7: launch_k_const64<7>(ndim, P, s); break;
+    case 8: launch_k_const64<8>(ndim, P, s); break;
+    case 9: launch_k_const64<9>(ndim, P, s); break;
+    case 10: launch_k_const64<10>(ndim, P, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sw

@@ -123,12 +123,15 @@ sw_status build_layout(sw_plan *p)
     }
     p->damp_n = int(maxd2 + 1);
     p->damp.assign(2 * size_t(p->damp_n), 0.0f);
+    p->damp64.assign(2 * size_t(p->damp_n), 0.0);
     for (int d2 = 0; d2 < p->damp_n; ++d2) {
         const double d = std::sqrt(double(d2));
         const double eta = (d2 == 0) ? 0.0 : q.damp_alpha * std::pow(d, q.damp_power);
         const double e = eta * q.dt;
-        p->damp[2 * d2] = float(1.0 / (1.0 + e));
-        p->damp[2 * d2 + 1] = float((1.0 - e) / (1.0 + e));
+        p->damp64[2 * d2] = 1.0 / (1.0 + e);
+        p->damp64[2 * d2 + 1] = (1.0 - e) / (1.0 + e);
+        p->damp[2 * d2] = float(p->damp64[2 * d2]);
+        p->damp[2 * d2 + 1] = float(p->damp64[2 * d2 + 1]);
     }
     build_workspace_map(p);
     return SW_OK;
@@ -143,10 +146,12 @@ void build_workspace_map(sw_plan *p)
         off += (bytes + 255) / 256 * 256;
         return o;
     };
-    const size_t fb = size_t(p->field_elems) * sizeof(float);
+    // values are 4 bytes, or 8 for a double-precision plan
+    const size_t es = p->prob.dtype == SW_F64 ? sizeof(double) : sizeof(float);
+    const size_t fb = size_t(p->field_elems) * es;
     w.model_k = take(fb);
     w.model_aux = (p->prob.scheme != SW_CONST) ? take(fb) : 0;
-    w.damp = take(size_t(p->damp_n) * 2 * sizeof(float));
+    w.damp = take(size_t(p->damp_n) * 2 * es);
     w.counter = take(sizeof(uint32_t));
     auto pts = [&](const PointSet &ps, WorkspaceMap::Pts &o) {
         const size_t ne = std::max<size_t>(1, ps.node.size());
@@ -156,14 +161,14 @@ void build_workspace_map(sw_plan *p)
         o.pid = take(ne * sizeof(int32_t));
         o.d2 = take(ne * sizeof(int32_t));
         o.phys = take(ne * sizeof(int64_t));
-        o.weight = take(ne * sizeof(float));
+        o.weight = take(ne * es);
         o.unode = take(nu * sizeof(int64_t));
         o.uptr = take((nu + 1) * sizeof(int32_t));
         o.uent = take(ne * sizeof(int32_t));
-        o.coef_a = take(ne * sizeof(float));
-        o.coef_s = take(ne * sizeof(float));
-        o.wscaled = take(ne * sizeof(float));
-        o.inj = take(2 * nu * sizeof(float));
+        o.coef_a = take(ne * es);
+        o.coef_s = take(ne * es);
+        o.wscaled = take(ne * es);
+        o.inj = take(2 * nu * es);
     };
     pts(p->src, w.src);
     pts(p->rec, w.rec);
@@ -335,6 +340,7 @@ sw_status build_points(sw_plan *p, PointSet &ps, int count, const double *coords
                         out.d2.push_back(int32_t(d2));
                         out.phys.push_back(phys);
                         out.weight.push_back(float(w));
+                        out.weight64.push_back(w);
                     }
         }
         out.ptr.push_back(int32_t(out.node.size()));

@@ -31,6 +31,7 @@ struct PointSet {
     std::vector<int32_t> d2;             // squared layer distance of the node (damping index)
     std::vector<int64_t> phys;           // physical-grid index the node copies its model from
     std::vector<float> weight;           // interpolation weight
+    std::vector<double> weight64;        // the same weight in double precision (SW_F64 plans)
     // the same entries grouped by unique node (CSR by node, deterministic gather)
     std::vector<int64_t> unode;          // unique nodes
     std::vector<int32_t> uptr;           // nunique + 1
@@ -85,6 +86,7 @@ struct sw_plan {
     double mp[sw::kMaxRadius + 1] = {};   // midpoint interpolation
     // damping table (A, B) by squared layer distance
     std::vector<float> damp;      // 2 * damp_n
+    std::vector<double> damp64;   // the same (A, B) pairs in double precision
     int damp_n = 1;
     sw::PointSet src, rec;
     sw::WorkspaceMap ws;

@@ -51,6 +51,15 @@ __device__ __forceinline__ float leapfrog(float a, float b, float k, float lap, 
     return fmaf(a, fmaf(k, lap, 2.0f * c), -(b * prev));
 }
 
+__device__ __forceinline__ double leapfrog(double a, double b, double k, double lap, double c, double prev)
+{
+    return fma(a, fma(k, lap, 2.0 * c), -(b * prev));
+}
+
+// Fused multiply-add of either value type.
+__device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
+
 // Buffer addressing: a resource descriptor (base, byte size) per array and
 // per z window, a per-thread 32-bit byte offset inside a plane and a uniform
 // (scalar) byte offset of the plane, so that a load costs no vector address
@@ -77,6 +86,44 @@ __device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, int voff)
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
 }
 
+// The same accesses for a value type T (float: the functions above; double:
+// 8-byte loads and stores, 16-byte damping pairs).
+template <typename T, int NT>
+__device__ __forceinline__ T buf_ldt(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    if constexpr (sizeof(T) == 4) return buf_ld<NT>(r, voff, soff);
+    else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, NT ? 2 : 0));
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void buf_stt(T v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    if constexpr (sizeof(T) == 4) {
+        buf_st<NT>(v, r, voff, soff);
+    } else {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, NT ? 2 : 0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ typename Pair<T>::type buf_ld2t(__amdgpu_buffer_rsrc_t r, int voff)
+{
+    if constexpr (sizeof(T) == 4) return buf_ld2(r, voff);
+    else return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+}
+
+// keep a loaded value (mask ~0) or replace it by +0 (mask 0)
+__device__ __forceinline__ float keep_mask(float v, unsigned m)
+{
+    return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m);
+}
+__device__ __forceinline__ double keep_mask(double v, unsigned m)
+{
+    return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, v) &
+                                          ((unsigned long long)(m) << 32 | m));
+}
+
 // Register-queue length of the block tile: at least 2R + 1 planes, rounded
 // up to a multiple of the slot and LDS-buffer periods so that a fully
 // unrolled round of Q planes addresses every queue entry, load slot and LDS
@@ -89,10 +136,13 @@ constexpr int queue_len()
 }
 
 // One tile (TX x 64 columns, one z chunk) of one grid; `bid` is the tile's
-// index in (z chunk, x tile, y tile) order.
-template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
-__device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
+// index in (z chunk, x tile, y tile) order.  T: value type (float, or double
+// for the double-precision forward).
+template <typename T, int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
+__device__ __forceinline__ void const_tile(const StencilParamsT<T> &P, int bid)
 {
+    using T2 = typename Pair<T>::type;
+    constexpr int ES = int(sizeof(T));           // bytes per value
     static_assert(TX % NW == 0, "rows must split evenly over waves");
     static_assert(PF == 1 || PF == 2, "one or two planes of loads in flight");
     constexpr int RPT = TX / NW;                 // rows per thread
@@ -104,7 +154,7 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     constexpr int YHN = (TX * 2 * R + NTH - 1) / NTH;               // y-halo items per thread
     constexpr int NS = PF + 1;                   // load slots
     constexpr int Q = queue_len<R, PF>();
-    __shared__ float lds[2][LX + 1][LY];          // row LX: sink for idle halo lanes
+    __shared__ T lds[2][LX + 1][LY];              // row LX: sink for idle halo lanes
 
     const Geom &g = P.g;
     const int lane = threadIdx.x & 63;
@@ -126,13 +176,13 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     // masked to zero)
     const int zw = zb - R;
     const int zt = ze + R;
-    const int pb = int(sz) * 4;
+    const int pb = int(sz) * ES;
     const uint32_t wbytes = uint32_t(zt - zw) * uint32_t(pb);
     const int64_t w0 = g.base + int64_t(zw) * sz;
     const auto rc = buf_res(P.cur + w0, wbytes);
     const auto rn = buf_res(P.nxt + w0, wbytes);
     const auto rk = buf_res(P.K + w0, wbytes);
-    const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
+    const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * uint32_t(sizeof(T2)));
     __amdgpu_buffer_rsrc_t rs = rk, rg = rk;
     if constexpr (MODE != MODE_FWD) rs = buf_res(P.store + w0, wbytes);
     if constexpr (MODE == MODE_IMAGE) rg = buf_res(P.grad + w0, wbytes);
@@ -143,12 +193,10 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         return axis_read(z, g.Z, P.bcm[0][0], P.bcm[0][1], P.gh) ? ~0u : 0u;
     };
     auto zdir = [&](int z) -> bool { return axis_dirichlet(z, g.Z, P.bcm[0][0], P.bcm[0][1]); };
-    // keep a loaded value (mask ~0) or replace it by +0 (mask 0)
-    auto keep = [](float v, unsigned m) -> float { return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & m); };
-    // in-plane byte offsets: (xy0 + x py + y) * 4; nodes off the grid (other than
-    // mirror ghosts, for reads) get an offset past every window, so their loads
-    // read zero and their stores are dropped
-    auto off = [&](int x, int yy) -> int { return (g.xy0 + x * g.py + yy) * 4; };
+    // in-plane byte offsets: (xy0 + x py + y) * ES; nodes off the grid (other
+    // than mirror ghosts, for reads) get an offset past every window, so their
+    // loads read zero and their stores are dropped
+    auto off = [&](int x, int yy) -> int { return (g.xy0 + x * g.py + yy) * ES; };
     constexpr int kOut = 0x7ffffe00;
     auto rd_ok = [&](int x, int yy) -> bool {
         return axis_read(x, g.X, P.bcm[1][0], P.bcm[1][1], P.gh) &&
@@ -199,23 +247,23 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
     }
 
     // q[i][(u + k) % Q] = p^n at plane z - R + k (k = 0 .. 2R) in unrolled step u
-    float q[RPT][Q];
+    T q[RPT][Q];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
         const int z = zb - R + k;
         const unsigned zm = zmask(z);
         const int so = soff(z);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) q[i][k] = keep(buf_ld<0>(rc, rr[i], so), zm);
+        for (int i = 0; i < RPT; ++i) q[i][k] = keep_mask(buf_ldt<T, 0>(rc, rr[i], so), zm);
     }
 
     struct Slot {
-        float f[RPT], p[RPT], k[RPT], d[RPT], g[RPT];
-        float2 ab[RPT];
-        float hx[HXN > 0 ? HXN : 1], hy[YHN];
+        T f[RPT], p[RPT], k[RPT], d[RPT], g[RPT];
+        T2 ab[RPT];
+        T hx[HXN > 0 ? HXN : 1], hy[YHN];
     };
     Slot S[NS];
-    auto load = [&](int z, Slot &T) {
+    auto load = [&](int z, Slot &L) {
         const int zf = z + R;
         const unsigned fm = zmask(zf);
         const int so = soff(z), sf = soff(zf);
@@ -223,25 +271,25 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
         // (A, B) by squared layer distance (entry 0 is (1, 1)); skipped on interior tile planes
         if (!inner_xy || ez > 0) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) T.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
+            for (int i = 0; i < RPT; ++i) L.ab[i] = buf_ld2t<T>(rd, (ez * ez + ex2[i]) * int(sizeof(T2)));
         } else {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) T.ab[i] = make_float2(1.0f, 1.0f);
+            for (int i = 0; i < RPT; ++i) L.ab[i] = T2{T(1), T(1)};
         }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            T.f[i] = keep(buf_ld<0>(rc, rr[i], sf), fm);
-            T.p[i] = buf_ld<NT>(rn, ro[i], so);
-            T.k[i] = buf_ld<NT>(rk, ro[i], so);
+            L.f[i] = keep_mask(buf_ldt<T, 0>(rc, rr[i], sf), fm);
+            L.p[i] = buf_ldt<T, NT>(rn, ro[i], so);
+            L.k[i] = buf_ldt<T, NT>(rk, ro[i], so);
             if constexpr (MODE == MODE_IMAGE) {
-                T.d[i] = buf_ld<NT>(rs, ro[i], so);
-                T.g[i] = buf_ld<NT>(rg, ro[i], so);
+                L.d[i] = buf_ldt<T, NT>(rs, ro[i], so);
+                L.g[i] = buf_ldt<T, NT>(rg, ro[i], so);
             }
         }
 #pragma unroll
-        for (int s = 0; s < HXN; ++s) T.hx[s] = buf_ld<0>(rc, hxo[s], so);
+        for (int s = 0; s < HXN; ++s) L.hx[s] = buf_ldt<T, 0>(rc, hxo[s], so);
 #pragma unroll
-        for (int s = 0; s < YHN; ++s) T.hy[s] = buf_ld<0>(rc, hyo[s], so);
+        for (int s = 0; s < YHN; ++s) L.hy[s] = buf_ldt<T, 0>(rc, hyo[s], so);
     };
 
 #pragma unroll
@@ -254,38 +302,38 @@ __device__ __forceinline__ void const_tile(const StencilParams &P, int bid)
             if (z < ze) {
                 Slot &W = S[u % NS];
                 if (z + PF < ze) load(z + PF, S[(u + PF) % NS]);
-                float(*T)[LY] = lds[u % 2];
+                T(*Tl)[LY] = lds[u % 2];
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) q[i][(u + 2 * R) % Q] = W.f[i];
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) T[HXR + wave * RPT + i][R + lane] = q[i][(u + R) % Q];
+                for (int i = 0; i < RPT; ++i) Tl[HXR + wave * RPT + i][R + lane] = q[i][(u + R) % Q];
 #pragma unroll
-                for (int s = 0; s < HXN; ++s) T[hxrow[s]][R + lane] = W.hx[s];
+                for (int s = 0; s < HXN; ++s) Tl[hxrow[s]][R + lane] = W.hx[s];
 #pragma unroll
-                for (int s = 0; s < YHN; ++s) T[hyrow[s]][hycol[s]] = W.hy[s];
+                for (int s = 0; s < YHN; ++s) Tl[hyrow[s]][hycol[s]] = W.hy[s];
                 __syncthreads();
 
                 const int so = soff(z);
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int lx = HXR + wave * RPT + i, ly = R + lane;
-                    const float c = q[i][(u + R) % Q];
-                    float lap = P.c0 * c;
+                    const T c = q[i][(u + R) % Q];
+                    T lap = P.c0 * c;
 #pragma unroll
                     for (int j = 1; j <= R; ++j)
-                        lap = fmaf(P.cz[j], q[i][(u + R + j) % Q] + q[i][(u + R - j) % Q], lap);
+                        lap = fmat(P.cz[j], q[i][(u + R + j) % Q] + q[i][(u + R - j) % Q], lap);
                     if constexpr (NDIM == 3) {
 #pragma unroll
-                        for (int j = 1; j <= R; ++j) lap = fmaf(P.cx[j], T[lx + j][ly] + T[lx - j][ly], lap);
+                        for (int j = 1; j <= R; ++j) lap = fmat(P.cx[j], Tl[lx + j][ly] + Tl[lx - j][ly], lap);
                     }
 #pragma unroll
-                    for (int j = 1; j <= R; ++j) lap = fmaf(P.cy[j], T[lx][ly + j] + T[lx][ly - j], lap);
-                    float out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, c, W.p[i]);
-                    if (rdir[i] || zdir(z)) out = 0.0f;     // held by a Dirichlet condition
-                    buf_st<NT>(out, rn, ro[i], so);
-                    if constexpr (MODE == MODE_STORE) buf_st<NT>(W.k[i] * lap, rs, ro[i], so);
+                    for (int j = 1; j <= R; ++j) lap = fmat(P.cy[j], Tl[lx][ly + j] + Tl[lx][ly - j], lap);
+                    T out = leapfrog(W.ab[i].x, W.ab[i].y, W.k[i], lap, c, W.p[i]);
+                    if (rdir[i] || zdir(z)) out = T(0);     // held by a Dirichlet condition
+                    buf_stt<T, NT>(out, rn, ro[i], so);
+                    if constexpr (MODE == MODE_STORE) buf_stt<T, NT>(W.k[i] * lap, rs, ro[i], so);
                     if constexpr (MODE == MODE_IMAGE)
-                        buf_st<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), rg, ro[i], so);
+                        buf_stt<T, NT>(fmat(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), rg, ro[i], so);
                 }
             }
         }
@@ -488,7 +536,7 @@ constexpr int const_min_waves()
 template <int R, int NDIM, int TX, int NW, int MODE, int NT, int PF>
 __global__ void __launch_bounds__(64 * NW, (const_min_waves<R, TX, NW>())) k_const(StencilParams P)
 {
-    const_tile<R, NDIM, TX, NW, MODE, NT, PF>(P, xcd_remap(blockIdx.x, gridDim.x));
+    const_tile<float, R, NDIM, TX, NW, MODE, NT, PF>(P, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Many grids (shots) in one persistent launch: the tiles of all shots form
@@ -515,7 +563,7 @@ __global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__
             P.cur = P.nxt;
             P.nxt = c;
         }
-        const_tile<R, NDIM, TX, NW, MODE_FWD, NT, PF>(P, t - tile_start[lo]);
+        const_tile<float, R, NDIM, TX, NW, MODE_FWD, NT, PF>(P, t - tile_start[lo]);
         __syncthreads();                      // LDS is reused by the next tile
     }
 }

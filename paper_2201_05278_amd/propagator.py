@@ -65,7 +65,7 @@ class Propagator:
     """One plan: grid, scheme, time axis, absorbing layer, geometry, model."""
 
     def __init__(self, n, h, space_order, dt, nsteps, scheme="const", nbl=0, alpha=0.001,
-                 power=3.0, device="cuda", bc=None):
+                 power=3.0, device="cuda", bc=None, dtype="float32"):
         ndim = len(n)
         prob = L.Problem()
         prob.ndim = ndim
@@ -85,6 +85,11 @@ class Propagator:
         prob.damp_power = float(power)
         prob.dt = float(dt)
         prob.nsteps = int(nsteps)
+        if dtype not in ("float32", "float64"):
+            raise ValueError("dtype must be 'float32' or 'float64'")
+        prob.dtype = 1 if dtype == "float64" else 0
+        self.dtype = dtype
+        self.torch_dtype = torch.float64 if dtype == "float64" else torch.float32
         self.prob = prob
         self.ndim = ndim
         self.n = tuple(int(x) for x in n)
@@ -119,7 +124,7 @@ class Propagator:
         return tuple(lay.dims[:self.ndim])
 
     def new_field(self):
-        return torch.zeros(self.layout.field_elems, dtype=torch.float32, device=self.device)
+        return torch.zeros(self.layout.field_elems, dtype=self.torch_dtype, device=self.device)
 
     def grid_view(self, buf):
         """Extended-grid view of a padded-layout buffer (no copy)."""
@@ -171,6 +176,8 @@ class Propagator:
 
     def prepare(self, vel, rho=None, cmax=None):
         """Build the device model arrays from physical-grid velocity (and density)."""
+        if self.dtype == "float64":
+            return self._prepare64(vel, cmax)
         vel = vel.to(self.device, torch.float32).contiguous()
         if rho is not None:
             rho = rho.to(self.device, torch.float32).contiguous()
@@ -186,6 +193,48 @@ class Propagator:
         self._vel = vel
         self._rho = rho
         return self
+
+    def _prepare64(self, vel, cmax):
+        vel = vel.to(self.device, torch.float64).contiguous()
+        if tuple(vel.shape) != self.n:
+            raise ValueError(f"velocity shape {tuple(vel.shape)} != grid {self.n}")
+        nbytes = int(self.layout.workspace_bytes)
+        if self.workspace is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        cmax = float(vel.max().item()) if cmax is None else float(cmax)
+        L.check("sw_model_prepare_f64", L.lib().sw_model_prepare_f64(
+            self._plan, _ptr(vel), cmax, _ptr(self.workspace), _stream()))
+        self._vel = vel
+        self._rho = None
+        return self
+
+    def _forward64(self, wavelet, saving_stride, fields, step0, nsteps_run, traces):
+        lay = self.layout
+        nrun = self.nsteps - step0 if nsteps_run is None else int(nsteps_run)
+        self._keep = None
+        if fields is None:
+            fields = (self.new_field(), self.new_field())
+        if lay.nsrc:
+            wavelet = wavelet.to(self.device, torch.float64).reshape(self.nsteps, lay.nsrc).contiguous()
+        if traces is None:
+            traces = torch.zeros((self.nsteps, max(0, lay.nrec)), dtype=torch.float64, device=self.device)
+        snaps = None
+        if saving_stride:
+            snaps = torch.zeros((self.nsteps // saving_stride,) + self.grid_shape, dtype=torch.float64,
+                                device=self.device)
+        io = L.Fwd64IO()
+        io.workspace = _ptr(self.workspace).value
+        io.wavelet = _ptr(wavelet if lay.nsrc else None).value
+        io.field[0] = fields[0].data_ptr()
+        io.field[1] = fields[1].data_ptr()
+        io.traces = traces.data_ptr() if lay.nrec else None
+        io.snaps = snaps.data_ptr() if snaps is not None else None
+        io.saving_stride = int(saving_stride)
+        io.step0 = int(step0)
+        io.nsteps_run = nrun
+        self._keep = (wavelet, fields, traces, snaps)
+        L.check("sw_forward_f64", L.lib().sw_forward_f64(self._plan, ctypes.byref(io), _stream()))
+        return ForwardResult(traces, fields, nrun % 2, snaps, None, 0)
 
     # ---- tiling -------------------------------------------------------------
     def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0, ts=0, occ=-1):
@@ -244,6 +293,10 @@ class Propagator:
         launch's duration (the call then waits for the GPU)."""
         if self._vel is None:
             raise RuntimeError("prepare() must be called after the geometry is set")
+        if self.dtype == "float64":
+            if checkpoint_every or use_graph or stencil_ms is not None or check_finite:
+                raise ValueError("the double-precision forward has no checkpoints, graphs, timing or checks")
+            return self._forward64(wavelet, saving_stride, fields, step0, nsteps_run, traces)
         lay = self.layout
         nrun = self.nsteps - step0 if nsteps_run is None else int(nsteps_run)
         # drop the previous call's buffers first, so that the allocator can

@@ -270,3 +270,23 @@ def test_adjoint_scheme_contract():
     stag = Propagator((20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered", nbl=2)
     st = L.lib().sw_adjoint(stag._plan, ctypes.byref(io), None)
     assert L.STATUS[st] == "SW_ERR_STATE"
+
+
+def test_double_precision_contract():
+    # a double-precision plan: constant density only; it is served by the _f64
+    # entry points and refused by the single-precision ones (and vice versa)
+    _expect("SW_ERR_UNSUPPORTED", Propagator, (20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, scheme="vd_staggered",
+            dtype="float64")
+    p64 = Propagator((20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, nbl=2, dtype="float64")
+    p32 = Propagator((20, 24, 28), (10.0,) * 3, 8, 1e-3, 5, nbl=2)
+    # doubles in the workspace
+    assert p64.layout.workspace_bytes > p32.layout.workspace_bytes
+    st = L.lib().sw_model_prepare(p64._plan, ctypes.c_void_p(256), None, 2000.0, ctypes.c_void_p(256), None)
+    assert L.STATUS[st] == "SW_ERR_STATE"
+    st = L.lib().sw_model_prepare_f64(p32._plan, ctypes.c_void_p(256), 2000.0, ctypes.c_void_p(256), None)
+    assert L.STATUS[st] == "SW_ERR_STATE"
+    io = L.FwdIO()
+    st = L.lib().sw_forward(p64._plan, ctypes.byref(io), None)
+    assert L.STATUS[st] in ("SW_ERR_STATE", "SW_ERR_ARG")
+    _expect("SW_ERR_UNSUPPORTED", p64.set_tiling, 16, 4)
+    assert p64.tiling["tx"] == 8

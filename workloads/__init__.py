@@ -31,6 +31,17 @@ structure of the configurations listed in the benchmark plan:
 
 Every configuration adds a 40-cell absorbing layer on each side.  Sizes can be
 scaled down for tests with the `n` / `nsteps` arguments.
+
+The paper's own benchmark shapes ("Performance evaluation", with the boundary
+set-up of its two examples) are stand-ins too (the Marmousi2 and Overthrust
+models are not used):
+
+  paper_shape_2d   351 x 1701 physical nodes, h = 10 m, layer 70 cells on the
+                   bottom and both sides, none on top; Neumann top, Dirichlet
+                   elsewhere; 6 flat layers 1500..4700 m/s + N(0, 20^2)
+                   (seed 7, capped at 4700); 101 receivers at 10 m depth.
+  paper_shape_3d   207 x 801 x 801 nodes, h = 20 m, no layer; Neumann top,
+                   Dirichlet elsewhere; the same recipe up to 6000 m/s.
 """
 from dataclasses import dataclass, field
 
@@ -58,6 +69,7 @@ class Workload:
     rec_interp: str = "hicks"
     radius: int = 4
     extra: dict = field(default_factory=dict)
+    bc: tuple = None                # per axis (low, high) ghost condition, None: zero ghosts
 
     @property
     def cmax(self):
@@ -171,3 +183,38 @@ def batch_3d(nshots=64, nsteps=1000, h=10.0, seed=4, nrec_side=64, size_scale=1.
         shots.append(Workload(f"shot{s}", (nz, nx, ny), (h, h, h), 8, nsteps, f, vel,
                               src=src, rec=rec))
     return shots
+
+
+def _paper_layers(n, cmax, seed=7):
+    rng = np.random.default_rng(seed)
+    speeds = np.linspace(1500.0, cmax, 6)
+    vel = layered(n, list(speeds))
+    return np.minimum(vel + rng.normal(0.0, 20.0, n).astype(np.float32), np.float32(cmax)).astype(np.float32)
+
+
+def paper_shape_2d(space_order=8, nsteps=None, tf=2.0):
+    """The 2D benchmark shape (421 x 1841 nodes with the layer); nsteps None:
+    the caller takes the step count from the stability limit and tf."""
+    n, h, cmax = (351, 1701), 10.0, 4700.0
+    vel = _paper_layers(n, cmax)
+    ext = [h * (k - 1) for k in n]
+    src = np.array([[2 * h, ext[1] / 2]])
+    rec = np.array([[h, ext[1] * (i / 100.0)] for i in range(101)])
+    wl = Workload("paper_shape_2d", n, (h, h), space_order, nsteps or 0, 10.0, vel,
+                  nbl=((0, 70), (70, 70)), src=src, rec=rec, src_interp="linear", rec_interp="linear",
+                  extra={"cmax": cmax, "tf": tf},
+                  bc=(("neumann", "dirichlet"), ("dirichlet", "dirichlet")))
+    return wl
+
+
+def paper_shape_3d(space_order=8, nsteps=None, tf=4.0):
+    """The 3D benchmark shape (207 x 801 x 801 nodes, no layer)."""
+    n, h, cmax = (207, 801, 801), 20.0, 6000.0
+    vel = _paper_layers(n, cmax)
+    ext = [h * (k - 1) for k in n]
+    src = np.array([[2 * h, ext[1] / 2, ext[2] / 2]])
+    rec = np.array([[h, ext[1] * (i / 100.0), ext[2] / 2] for i in range(101)])
+    return Workload("paper_shape_3d", n, (h, h, h), space_order, nsteps or 0, 10.0, vel,
+                    nbl=((0, 0), (0, 0), (0, 0)), src=src, rec=rec, src_interp="linear", rec_interp="linear",
+                    extra={"cmax": cmax, "tf": tf},
+                    bc=(("neumann", "dirichlet"), ("dirichlet", "dirichlet"), ("dirichlet", "dirichlet")))
