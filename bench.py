@@ -21,7 +21,7 @@ the fused absorbing layer, source injection and receiver recording.
                    workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       python bench.py --profile-pass     (5 forward steps + a 1 GiB copy, for counters)
+       python bench.py --profile-pass {const,vd,vd_adjoint}   (a short run + a 1 GiB copy, for counters)
        python bench.py --paper-shapes     (whole runs at the paper's Table 2 / 3 shapes)
 """
 import argparse
@@ -133,20 +133,29 @@ def batch_leg(nsteps, cache):
 
 
 def profile_pass(args):
-    """A short run for hardware counters: 5 forward steps of the workload with
-    the default tiling, then a plain 1 GiB device copy of known size."""
+    """A short run for hardware counters with the default tiling: 5 forward
+    steps of the workload (constant density, or the staggered scheme), or a
+    10-step staggered forward + adjoint with checkpoints every 5 steps; then a
+    plain 1 GiB device copy of known size."""
     import torch
     import workloads
     from paper_2201_05278_amd import critical_dt, ricker
-    wl = workloads.smooth_3d(n=args.n, nsteps=6, scheme="vd_staggered")
+    kind = args.profile_pass
+    wl = workloads.smooth_3d(n=args.n, nsteps=10, scheme="vd_staggered")
     dt = workloads.CFL_FRACTION * critical_dt(wl.h, wl.space_order, wl.cmax)
-    prop = make_prop(wl, "const", 6, dt)
-    prop.forward(ricker(wl.f_peak, dt, 6).reshape(-1, 1).cuda(), nsteps_run=5)
+    wav = ricker(wl.f_peak, dt, 10).reshape(-1, 1).cuda()
+    if kind == "vd_adjoint":
+        prop = make_prop(wl, "vd_staggered", 10, dt)
+        time_fwd_adjoint(prop, wav, 5)
+    else:
+        prop = make_prop(wl, "const" if kind == "const" else "vd_staggered", 10, dt)
+        prop.forward(wav, nsteps_run=5)
+    del prop
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print("profile pass done: 5 steps of the 592^3 forward, 1 GiB copy", flush=True)
+    print(f"profile pass done: {kind} at {args.n + 80}^3, 1 GiB copy", flush=True)
 
 
 # The paper's benchmark shapes ("Performance evaluation", Tables 2 and 3) with
@@ -251,7 +260,8 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "simwave_tune.json"))
-    ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--profile-pass", choices=["const", "vd", "vd_adjoint"], default=None,
+                    help="a short run for hardware counters (no JSON line)")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="whole runs at the paper's benchmark shapes instead of the headline")
     args = ap.parse_args()

@@ -338,9 +338,12 @@ sw_status sw_adjoint(sw_plan *plan, const sw_adj_io *io, void *stream);
  *           launch reserves 160 KiB / occ of LDS per block, so that fewer
  *           z streams share each L2 (3 .. 6; 0: no cap; -1: default).  The
  *           cap only lowers occupancy; where registers or LDS already allow
- *           fewer blocks it has no effect.  Other values: SW_ERR_ARG. */
+ *           fewer blocks it has no effect.  Other values: SW_ERR_ARG.
+ *   order   block order of single-step block tiles within a z chunk: 0
+ *           default, 1 y tiles fastest, 2 x tiles fastest (tiles that share
+ *           the taller x halos then run side by side on an XCD). */
 typedef struct sw_tiling {
-    int32_t tx, nw, zc, nt, pf, wt, ts, occ;
+    int32_t tx, nw, zc, nt, pf, wt, ts, occ, order;
 } sw_tiling;
 
 /* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan. */

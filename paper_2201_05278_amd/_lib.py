@@ -74,7 +74,7 @@ class AdjIO(ctypes.Structure):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("tx", c_int32), ("nw", c_int32), ("zc", c_int32), ("nt", c_int32), ("pf", c_int32),
-                ("wt", c_int32), ("ts", c_int32), ("occ", c_int32)]
+                ("wt", c_int32), ("ts", c_int32), ("occ", c_int32), ("order", c_int32)]
 
 
 class BatchIO(ctypes.Structure):

@@ -172,6 +172,8 @@ Tiling choose_tiling(const sw_plan *p)
     t.pf = p->tile_pf ? p->tile_pf : kDefaultPF;
     // the occupancy cap applies to single-step block tiles
     t.occ = (t.wt || t.ts == 2) ? 0 : (p->tile_occ < 0 ? def_occ : p->tile_occ);
+    // block order: y tiles fastest unless x tiles fastest is asked (block tiles only)
+    t.xfast = (t.wt || t.ts == 2) ? 0 : (p->tile_order == 2 ? 1 : 0);
     return t;
 }
 
@@ -213,6 +215,7 @@ void set_tiles(const sw_plan *p, const Tiling &t, StencilParams &P)
     P.ntx = (p->dims[1] + t.tx - 1) / t.tx;
     P.nty = (p->dims[2] + cols - 1) / cols;
     P.zc = std::min(t.zc, zmax);
+    P.xfast = t.xfast;
     P.nzc = (p->dims[0] + P.zc - 1) / P.zc;
 }
 
@@ -423,8 +426,9 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
     if (p->prob.dtype == SW_F64 && t)
         return fail(SW_ERR_UNSUPPORTED, "double-precision plans use their fixed tile shape");
-    sw_tiling d{0, 0, 0, -1, 0, 0, 0, -1};
+    sw_tiling d{0, 0, 0, -1, 0, 0, 0, -1, 0};
     if (t) d = *t;
+    if (d.order < 0 || d.order > 2) return fail(SW_ERR_ARG, "order must be 0 (default), 1 or 2");
     if (d.zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
     if (d.occ < -1 || d.occ == 1 || d.occ == 2 || d.occ > 6)
         return fail(SW_ERR_ARG, "occ must be -1 (default), 0 (no cap) or 3 .. 6");
@@ -458,6 +462,7 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
     p->tile_wt = d.wt ? 1 : 0;
     p->tile_ts = d.ts;
     p->tile_occ = d.occ;
+    p->tile_order = d.order;
     if (p->graph_exec) {
         (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
         p->graph_exec = nullptr;
@@ -470,7 +475,7 @@ sw_status sw_plan_get_tiling(const sw_plan *p, sw_tiling *out)
     set_error("");
     if (!p || !out) return fail(SW_ERR_ARG, "NULL argument");
     const Tiling t = choose_tiling(p);
-    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt, t.ts, t.occ};
+    *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt, t.ts, t.occ, t.xfast ? 2 : 1};
     return SW_OK;
 }
 

@@ -80,6 +80,7 @@ void fill_params64(const sw_plan *p, void *ws, StencilParamsT<double> &P)
     P.nty = (p->dims[2] + 63) / 64;
     P.zc = std::min(t.zc, zmax);
     P.nzc = (p->dims[0] + P.zc - 1) / P.zc;
+    P.xfast = t.xfast;
 }
 
 }  // namespace

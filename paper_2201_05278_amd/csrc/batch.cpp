@@ -365,7 +365,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     if (it != cache.end()) {
         auto &v = it->second;
         const sw_tiling t{v["tx"], v["nw"], v["zc"], v["nt"], v["pf"], v["wt"], v["ts"],
-                          v.count("occ") ? v["occ"] : -1};
+                          v.count("occ") ? v["occ"] : -1, v.count("order") ? v["order"] : 0};
         if (sw_plan_set_tiling(p, &t) == SW_OK) return SW_OK;
         // a cached choice this plan rejects (a stale or hand-edited entry): tune again
         set_error("");
@@ -389,7 +389,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     SW_HIP(hipEventCreate(&e0));
     SW_HIP(hipEventCreate(&e1));
     float best = std::numeric_limits<float>::max();
-    sw_tiling best_t{0, 0, 0, -1, 0, 0, 0, -1};
+    sw_tiling best_t{0, 0, 0, -1, 0, 0, 0, -1, 0};
     StencilParams P;
     fill_params(p, io->workspace, P);
     P.cur = io->field[0];
@@ -398,11 +398,14 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
         for (int zc : zc_candidates(p->dims[0], p->r))
             for (int nt : {0, 1})
                 for (int pf : {1, 2})
-                    for (int occ : {-1, 4}) {
+                    for (int occ : {-1, 4})
+                        for (int order : {1, 2}) {
                 // a cap of 4 blocks per CU is tried for single-step 4-wave block tiles
                 if (occ == 4 && (!const3 || sh.wt || sh.ts == 2 || sh.nw != 4 || p->ndim != 3)) continue;
                 if ((!const3 || sh.wt || sh.ts == 2) && pf == 2) continue;
-                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts, occ};
+                // the block order applies to single-step block tiles in 3D
+                if (order == 2 && (sh.wt || sh.ts == 2 || p->ndim != 3)) continue;
+                const sw_tiling cand{sh.tx, sh.nw, zc, nt, pf, sh.wt, sh.ts, occ, order};
                 st = sw_plan_set_tiling(p, &cand);
                 if (st != SW_OK) continue;
                 // per-step time: single sweeps, or two-step sweeps over half as many launches
@@ -429,7 +432,8 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
     st = sw_plan_set_tiling(p, &best_t);
     if (st != SW_OK) return st;
     cache[key] = {{"tx", best_t.tx}, {"nw", best_t.nw}, {"zc", best_t.zc}, {"nt", best_t.nt},
-                  {"pf", best_t.pf}, {"wt", best_t.wt}, {"ts", best_t.ts}, {"occ", best_t.occ}};
+                  {"pf", best_t.pf}, {"wt", best_t.wt}, {"ts", best_t.ts}, {"occ", best_t.occ},
+                  {"order", best_t.order}};
     write_cache(cache_path, cache);
     return SW_OK;
 }

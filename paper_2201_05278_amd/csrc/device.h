@@ -35,6 +35,21 @@ __device__ inline int xcd_remap(int bid, int n)
     return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
 }
 
+// Tile (tx, ty, z chunk) of block index bid: y tiles fastest, or x tiles
+// fastest (neighbours along x, which share the larger halos, then run side by
+// side on an XCD).
+__device__ inline void tile_of(int bid, int ntx, int nty, int xfast, int &tx, int &ty, int &zc)
+{
+    if (xfast) {
+        tx = bid % ntx;
+        ty = (bid / ntx) % nty;
+    } else {
+        ty = bid % nty;
+        tx = (bid / nty) % ntx;
+    }
+    zc = bid / (ntx * nty);
+}
+
 // Pair type of a value type: the (A, B) damping entries.
 template <typename T> struct Pair;
 template <> struct Pair<float> { using type = float2; };
@@ -59,6 +74,7 @@ struct StencilParamsT {
     T sz[11], sx[11], sy[11];   // staggered s_j / h, or centred c_j / h (first derivative)
     T mj[11];               // midpoint interpolation weights
     int ntx, nty, nzc, zc;  // tiling: tiles along x, y; z chunks and chunk length
+    int xfast;              // tile order within a z chunk: 1 x tiles fastest, 0 y tiles fastest
     int bcm[3][2];          // ghost condition per internal axis (z, x, y) and side: 0 zero, 1 Dirichlet, 2 Neumann
     int gh;                 // ghost layers held in the stored halo (mirror sides)
 };
@@ -99,6 +115,7 @@ struct Tiling {
     int wt;                 // 1: wave tiles (each wave owns tx / nw rows, no block barrier)
     int ts;                 // time steps per sweep (1, or 2 for the two-step constant-density sweep)
     int occ;                // resident blocks per CU at most (0: as registers and LDS allow; else 3..6)
+    int xfast;              // 1: x tiles fastest in the block order (block tiles, single steps)
 };
 
 // Dynamic LDS bytes that hold a kernel with `static_lds` bytes of its own to

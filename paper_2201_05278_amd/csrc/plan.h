@@ -94,7 +94,7 @@ struct sw_plan {
     void *prepared_ws = nullptr;
     // stencil tiling chosen by sw_plan_set_tiling / sw_plan_autotune (tx == 0: default)
     int tile_tx = 0, tile_nw = 0, tile_zc = 0, tile_nt = -1, tile_pf = 0, tile_wt = 0, tile_ts = 0,
-        tile_occ = -1;
+        tile_occ = -1, tile_order = 0;
     // bumped by every call that changes what a captured launch bakes in
     // (point tables and counts, model, tiling); part of the graph keys
     uint64_t generation = 1;

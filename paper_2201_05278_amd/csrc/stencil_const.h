@@ -159,10 +159,8 @@ __device__ __forceinline__ void const_tile(const StencilParamsT<T> &P, int bid)
     const Geom &g = P.g;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int ty = bid % P.nty;
-    const int rest = bid / P.nty;
-    const int tx = rest % P.ntx;
-    const int zc = rest / P.ntx;
+    int tx, ty, zc;
+    tile_of(bid, P.ntx, P.nty, P.xfast, tx, ty, zc);
     const int y0 = ty * 64;
     const int y = y0 + lane;
     const int x0 = tx * TX;
@@ -357,10 +355,8 @@ __device__ __forceinline__ void const_wave_tile(const StencilParams &P, int bid)
     const Geom &g = P.g;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int ty = bid % P.nty;
-    const int rest = bid / P.nty;
-    const int tx = rest % P.ntx;
-    const int zc = rest / P.ntx;
+    int tx, ty, zc;
+    tile_of(bid, P.ntx, P.nty, P.xfast, tx, ty, zc);
     const int y0 = ty * 64;
     const int y = y0 + lane;
     const int xw = tx * (RW * NWB) + wave * RW;     // first row of this wave

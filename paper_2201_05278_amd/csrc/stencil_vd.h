@@ -80,10 +80,8 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int ty = bid % P.nty;
-    const int rest = bid / P.nty;
-    const int tx = rest % P.ntx;
-    const int zc = rest / P.ntx;
+    int tx, ty, zc;
+    tile_of(bid, P.ntx, P.nty, P.xfast, tx, ty, zc);
     const int y0 = ty * 64;
     const int y = y0 + lane;
     const int x0 = tx * TX;
@@ -388,10 +386,8 @@ __global__ void __launch_bounds__(64 * NW) k_cent(StencilParams P)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int ty = bid % P.nty;
-    const int rest = bid / P.nty;
-    const int tx = rest % P.ntx;
-    const int zc = rest / P.ntx;
+    int tx, ty, zc;
+    tile_of(bid, P.ntx, P.nty, P.xfast, tx, ty, zc);
     const int y0 = ty * 64;
     const int y = y0 + lane;
     const int x0 = tx * TX;

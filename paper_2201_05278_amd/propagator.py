@@ -237,11 +237,12 @@ class Propagator:
         return ForwardResult(traces, fields, nrun % 2, snaps, None, 0)
 
     # ---- tiling -------------------------------------------------------------
-    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0, ts=0, occ=-1):
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=-1, pf=0, wt=0, ts=0, occ=-1, order=0):
         """Stencil tile shape, z-chunk length, cache policy, prefetch distance,
-        wave-tile mode, time steps per sweep and resident-block cap per CU
-        (0 / -1: default; occ=0: no cap)."""
-        t = L.Tiling(tx, nw, zc, nt, pf, wt, ts, occ)
+        wave-tile mode, time steps per sweep, resident-block cap per CU and
+        block order (0 / -1: default; occ=0: no cap; order 1: y tiles fastest,
+        2: x tiles fastest)."""
+        t = L.Tiling(tx, nw, zc, nt, pf, wt, ts, occ, order)
         L.check("sw_plan_set_tiling", L.lib().sw_plan_set_tiling(self._plan, ctypes.byref(t)))
 
     @property
