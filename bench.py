@@ -251,7 +251,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--adj-steps", type=int, default=2000)
     ap.add_argument("--ckpt-every", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--n", type=int, default=512)

@@ -163,3 +163,30 @@ def test_gradient320_two_shots():
           f"vs oracle {float(g['misfit']):.6e}", flush=True)
     assert abs(misfit - float(g["misfit"])) <= 1e-3 * float(g["misfit"])
     assert rel < 1e-3
+
+
+def test_headline_memory_plan_2000_steps_dot_product():
+    # The fwd+adjoint configuration of the headline grid whole: 592^3, 2000
+    # steps, checkpoints every 50 steps (40 checkpoint pairs, 66 GB, plus a
+    # 50-level segment, 41 GB, resident in HBM).  <F s, r> = <s, F^T r>, a
+    # property of the adjoint that holds at any size.
+    wl = workloads.smooth_3d(scheme="const")
+    nsteps, every = wl.nsteps, 50
+    dt = workloads.CFL_FRACTION * critical_dt(wl.h, wl.space_order, wl.cmax)
+    prop = Propagator(wl.n, wl.h, wl.space_order, dt, nsteps, nbl=wl.nbl)
+    prop.set_sources(wl.src, wl.src_interp)
+    prop.set_receivers(wl.rec, wl.rec_interp)
+    prop.prepare(torch.from_numpy(wl.vel).cuda(), cmax=wl.cmax)
+    print(f"case: 592^3 fwd+adjoint, {nsteps} steps, checkpoints every {every}, dot product", flush=True)
+    rng = np.random.default_rng(6)
+    s = torch.from_numpy(rng.standard_normal((nsteps, 1)).astype(np.float32)).cuda()
+    r = torch.from_numpy(rng.standard_normal((nsteps, len(wl.rec))).astype(np.float32)).cuda()
+    fw = prop.forward(s, checkpoint_every=every)
+    assert fw.ckpt.shape[0] == nsteps // every
+    out = prop.adjoint(s, r, fw.ckpt, every, want_src_adjoint=True)
+    torch.cuda.synchronize()
+    lhs = float((fw.traces.double() * r.double()).sum())
+    rhs = float((s.double() * out[1].double()).sum())
+    print(f"dot product: {lhs:.9e} vs {rhs:.9e}, rel {abs(lhs - rhs) / max(abs(lhs), abs(rhs)):.2e}", flush=True)
+    assert np.isfinite(lhs) and np.isfinite(rhs)
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs)), (lhs, rhs)
