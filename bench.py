@@ -108,6 +108,7 @@ def batch_leg(nsteps, cache):
         nodes += float(np.prod([k + 2 * wl.nbl for k in wl.n]))
     batch = Batch(props)
     batch.autotune(wavs, cache)
+    tiling = batch.tiling
     # untimed first run: captures and instantiates the graph of the whole loop,
     # so that the timed call only replays it
     batch.forward(wavs, use_graph=True)
@@ -129,7 +130,7 @@ def batch_leg(nsteps, cache):
     return {"shots": len(props), "steps": nsteps, "nodes_per_step": int(nodes),
             "batched_gpts": round(nodes * nsteps / t_batch / 1e9, 3),
             "single_loop_gpts": round(nodes * nsteps / t_loop / 1e9, 3),
-            "speedup": round(t_loop / t_batch, 3)}
+            "speedup": round(t_loop / t_batch, 3), "tiling": tiling}
 
 
 def profile_pass(args):

@@ -358,11 +358,19 @@ typedef struct sw_batch sw_batch;
 /* Group `nshots` prepared constant-density plans (each with its own grid
  * size, dt, model, geometry and workspace; all with the same ndim, space
  * order and step count) so that every time step advances all shots with one
- * persistent stencil launch over a tile list spanning all shots, one batched
+ * stencil launch over a tile list spanning all shots, one batched
  * injection and one batched recording launch.  The plans stay owned by the
  * caller and must outlive the batch. */
 sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out);
 sw_status sw_batch_destroy(sw_batch *batch);
+/* Tiling of the batch stencil launch (t NULL: the defaults) and its grid:
+ * blocks_per_cu > 0 persistent blocks per compute unit looping over the tile
+ * list, -1 one block per tile, 0 the default (one block per tile for 3D
+ * shots, 8 looping blocks per compute unit for 2D shots).  Plain tile
+ * shapes only (wt 0, ts 1, occ 0; order is ignored; zc 0: the default chunk).
+ * Results do not depend on any of it. */
+sw_status sw_batch_set_tiling(sw_batch *batch, const sw_tiling *t, int32_t blocks_per_cu);
+sw_status sw_batch_get_tiling(const sw_batch *batch, sw_tiling *out, int32_t *blocks_per_cu);
 /* Bytes of the device descriptor table the caller allocates for the batch. */
 sw_status sw_batch_layout(const sw_batch *batch, int64_t *table_bytes);
 
@@ -395,7 +403,7 @@ sw_status sw_batch_forward_static(sw_batch *batch, const sw_batch_io *io, void *
 /* Pick the tile shape (rows per tile, waves per block), the z-chunk length,
  * cache policy and prefetch depth, for single plans also the two-step sweep
  * (when io->field2 is given) and a cap of 4 resident blocks per CU, and (for
- * batches) the persistent grid size, by timing a few steps of each
+ * batches) the launch grid (one block per tile or a looping grid), by timing a few steps of each
  * candidate on the given buffers (their contents are overwritten), or reuse
  * the choice stored under the same problem key in the JSON file `cache_path`
  * (may be NULL: no cache).  The choice is kept in the plan / batch and

@@ -108,6 +108,8 @@ SIGNATURES = {
     "sw_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "sw_batch_destroy": (c_int32, [c_void_p]),
     "sw_batch_layout": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
+    "sw_batch_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling), c_int32]),
+    "sw_batch_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling), ctypes.POINTER(c_int32)]),
     "sw_batch_forward": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), c_void_p]),
     "sw_batch_forward_static": (c_int32, [c_void_p, ctypes.POINTER(BatchIO), c_void_p]),
     "sw_plan_autotune": (c_int32, [c_void_p, ctypes.POINTER(FwdIO), ctypes.c_char_p, c_void_p]),

@@ -535,11 +535,11 @@ __global__ void __launch_bounds__(64 * NW, (const_min_waves<R, TX, NW>())) k_con
     const_tile<float, R, NDIM, TX, NW, MODE, NT, PF>(P, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-// Many grids (shots) in one persistent launch: the tiles of all shots form
-// one list (shot s owns [tile_start[s], tile_start[s+1])); each block takes
-// tiles blockIdx, blockIdx + gridDim, ... (XCD-aware), looks up the shot and
-// runs the same tile code on that shot's arrays.  `parity` swaps the two
-// wavefield buffers of every shot.
+// Many grids (shots) in one launch: the tiles of all shots form one list
+// (shot s owns [tile_start[s], tile_start[s+1])); each block takes tiles
+// blockIdx, blockIdx + gridDim, ... (XCD-aware; one tile when the grid has a
+// block per tile), looks up the shot and runs the same tile code on that
+// shot's arrays.  `parity` swaps the two wavefield buffers of every shot.
 template <int R, int NDIM, int TX, int NW, int NT, int PF>
 __global__ void __launch_bounds__(64 * NW) k_const_batch(const StencilParams *__restrict__ shots,
                                                          const int *__restrict__ tile_start,

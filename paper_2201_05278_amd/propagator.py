@@ -427,6 +427,22 @@ class Batch:
         self._shots = shots
         return io
 
+    def set_tiling(self, tx=0, nw=0, zc=0, nt=1, pf=1, blocks_per_cu=0):
+        """Tile shape, z-chunk length, cache policy and prefetch distance of the
+        batch launch, and its grid (blocks_per_cu 0: default persistent grid,
+        -1: one block per tile); tx 0: the defaults."""
+        t = L.Tiling(tx, nw, zc, nt, pf, 0, 1, 0, 1) if tx else None
+        L.check("sw_batch_set_tiling", L.lib().sw_batch_set_tiling(
+            self._batch, ctypes.byref(t) if t is not None else None, int(blocks_per_cu)))
+
+    @property
+    def tiling(self):
+        t, bpc = L.Tiling(), ctypes.c_int32()
+        L.check("sw_batch_get_tiling", L.lib().sw_batch_get_tiling(self._batch, ctypes.byref(t), ctypes.byref(bpc)))
+        out = {k: getattr(t, k) for k in ("tx", "nw", "zc", "nt", "pf")}
+        out["blocks_per_cu"] = bpc.value
+        return out
+
     def autotune(self, wavelets, cache_path=None):
         io = self._io(wavelets, self.props[0].nsteps, False)
         L.check("sw_batch_autotune", L.lib().sw_batch_autotune(

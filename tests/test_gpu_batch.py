@@ -60,6 +60,21 @@ def test_batch_matches_single_shots_bitwise():
         for k, p in enumerate(props):
             assert torch.equal(traces[k], single[k][0]), k
             assert torch.equal(p.grid_view(batch.fields[k][batch.current]), single[k][1]), k
+    # tilings and grids of the batch launch: one block per tile, a small
+    # persistent grid (many tiles per block) and the default
+    for cfg in [(24, 8, 11, 1, 1, -1), (8, 4, 0, 0, 2, 1), (16, 8, 7, 1, 1, 3), (32, 8, 100, 0, 1, -1),
+                (0, 0, 0, 1, 1, 0)]:
+        print(f"case: batch tiling {cfg}", flush=True)
+        batch.set_tiling(*cfg)
+        got = batch.tiling
+        if cfg[0]:
+            assert (got["tx"], got["nw"], got["blocks_per_cu"]) == (cfg[0], cfg[1], cfg[5])
+        for use_graph in (False, True):
+            traces = batch.forward(wavs, use_graph=use_graph)
+            torch.cuda.synchronize()
+            for k, p in enumerate(props):
+                assert torch.equal(traces[k], single[k][0]), k
+                assert torch.equal(p.grid_view(batch.fields[k][batch.current]), single[k][1]), k
 
 
 def test_autotune_keeps_results_and_uses_cache(tmp_path):
