@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsimwave_hip.so")
-SOURCES = ["plan.cpp", "api.cpp", "api64.cpp", "batch.cpp", "k_dispatch.cpp", "k_points.hip", "k_adjoint_vd.hip",
+SOURCES = ["plan.cpp", "api.cpp", "api64.cpp", "batch.cpp", "trace.cpp", "k_dispatch.cpp", "k_points.hip", "k_adjoint_vd.hip",
            "k_f64.hip"] + \
           [f"k_r{r}.hip" for r in range(1, 11)]
 FLAGS = [

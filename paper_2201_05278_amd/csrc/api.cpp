@@ -576,6 +576,7 @@ static sw_status upload_points(sw_plan *p, const PointSet &ps, const WorkspaceMa
 sw_status sw_model_prepare(sw_plan *p, const float *vel, const float *rho, double cmax, void *ws,
                            void *stream)
 {
+    Range range_("sw_model_prepare");
     set_error("");
     if (!p || !vel || !ws) return fail(SW_ERR_ARG, "NULL argument");
     if (p->prob.dtype == SW_F64) return fail(SW_ERR_STATE, "a double-precision plan is prepared by sw_model_prepare_f64");
@@ -773,6 +774,7 @@ static sw_status forward_impl(sw_plan *p, const sw_fwd_io *io, void *stream)
 
 sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
 {
+    Range range_("sw_forward");
     set_error("");
     sw_status st = forward_impl(p, io, stream);
     if (st != SW_OK || !io->check_finite) return st;
@@ -797,6 +799,7 @@ sw_status sw_forward(sw_plan *p, const sw_fwd_io *io, void *stream)
 
 sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
 {
+    Range range_("sw_adjoint");
     set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
     if (p->prob.scheme == SW_VD_CENTRED)

@@ -89,6 +89,7 @@ extern "C" {
 
 sw_status sw_model_prepare_f64(sw_plan *p, const double *vel, double cmax, void *ws, void *stream)
 {
+    Range range_("sw_model_prepare_f64");
     set_error("");
     if (!p || !vel || !ws) return fail(SW_ERR_ARG, "NULL argument");
     if (p->prob.dtype != SW_F64) return fail(SW_ERR_STATE, "a single-precision plan is prepared by sw_model_prepare");
@@ -120,6 +121,7 @@ sw_status sw_model_prepare_f64(sw_plan *p, const double *vel, double cmax, void 
 
 sw_status sw_forward_f64(sw_plan *p, const sw_fwd64_io *io, void *stream)
 {
+    Range range_("sw_forward_f64");
     set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
     if (p->prob.dtype != SW_F64) return fail(SW_ERR_STATE, "a single-precision plan runs by sw_forward");

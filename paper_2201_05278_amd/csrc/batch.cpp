@@ -38,6 +38,12 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// 16-row tiles of 4 waves, 64-plane chunks (3D); one row per tile in 2D.
+Tiling default_batch_tiling(int ndim)
+{
+    return ndim == 2 ? Tiling{1, 1, 64, 1, 1, 0} : Tiling{16, 4, 64, 1, 1, 0};
+}
+
 void batch_layout(sw_batch *b)
 {
     b->off_params = 0;
@@ -250,7 +256,7 @@ sw_status sw_batch_create(int32_t nshots, sw_plan *const *plans, sw_batch **out)
     b->r = p0->r;
     b->ndim = p0->ndim;
     b->nsteps = p0->prob.nsteps;
-    b->tiling = Tiling{p0->ndim == 2 ? 1 : 8, p0->ndim == 2 ? 1 : 4, 64, 1, 1, 0};
+    b->tiling = default_batch_tiling(p0->ndim);
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
@@ -276,7 +282,7 @@ sw_status sw_batch_set_tiling(sw_batch *b, const sw_tiling *t, int32_t blocks_pe
     if (!b) return fail(SW_ERR_ARG, "NULL argument");
     if (blocks_per_cu < -1 || blocks_per_cu > 64) return fail(SW_ERR_ARG, "blocks_per_cu must be in -1..64");
     if (!t) {
-        b->tiling = sw_batch{}.tiling;
+        b->tiling = default_batch_tiling(b->ndim);
         b->bpc = blocks_per_cu;
         return SW_OK;
     }
@@ -287,7 +293,7 @@ sw_status sw_batch_set_tiling(sw_batch *b, const sw_tiling *t, int32_t blocks_pe
                                     " is not instantiated");
     if (t->zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0 (0: the default)");
     if (t->pf != 1 && t->pf != 2) return fail(SW_ERR_ARG, "pf must be 1 or 2");
-    b->tiling = Tiling{t->tx, t->nw, t->zc ? t->zc : sw_batch{}.tiling.zc, t->nt ? 1 : 0, t->pf, 0};
+    b->tiling = Tiling{t->tx, t->nw, t->zc ? t->zc : default_batch_tiling(b->ndim).zc, t->nt ? 1 : 0, t->pf, 0};
     b->bpc = blocks_per_cu;
     return SW_OK;
 }
@@ -312,6 +318,7 @@ sw_status sw_batch_layout(const sw_batch *b, int64_t *table_bytes)
 
 sw_status sw_batch_forward(sw_batch *b, const sw_batch_io *io, void *stream)
 {
+    Range range_("sw_batch_forward");
     set_error("");
     if (!b || !io || !io->shots || !io->table) return fail(SW_ERR_ARG, "NULL argument");
     if (reinterpret_cast<uintptr_t>(io->table) % 256) return fail(SW_ERR_WORKSPACE, "table must be 256-byte aligned");
@@ -372,6 +379,7 @@ sw_status sw_batch_forward(sw_batch *b, const sw_batch_io *io, void *stream)
 
 sw_status sw_batch_forward_static(sw_batch *b, const sw_batch_io *io, void *stream)
 {
+    Range range_("sw_batch_forward_static");
     set_error("");
     if (!b || !io || !io->shots) return fail(SW_ERR_ARG, "NULL argument");
     if (io->use_graph)
@@ -391,6 +399,7 @@ sw_status sw_batch_forward_static(sw_batch *b, const sw_batch_io *io, void *stre
 
 sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_path, void *stream)
 {
+    Range range_("sw_plan_autotune");
     set_error("");
     if (!p || !io) return fail(SW_ERR_ARG, "NULL argument");
     if (p->prob.dtype == SW_F64) return fail(SW_ERR_UNSUPPORTED, "double-precision plans use their fixed tile shape");
@@ -479,6 +488,7 @@ sw_status sw_plan_autotune(sw_plan *p, const sw_fwd_io *io, const char *cache_pa
 
 sw_status sw_batch_autotune(sw_batch *b, const sw_batch_io *io, const char *cache_path, void *stream)
 {
+    Range range_("sw_batch_autotune");
     set_error("");
     if (!b || !io || !io->shots || !io->table) return fail(SW_ERR_ARG, "NULL argument");
     int64_t nodes = 0;

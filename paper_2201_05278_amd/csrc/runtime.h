@@ -40,6 +40,18 @@ bool two_step_ready(const sw_plan *p, const sw_fwd_io *io);
 hipError_t stencil_two(const sw_plan *p, const sw_fwd_io *io, int n, const float *cur, const float *prv,
                        float *out1, float *out2, bool sources, hipStream_t s);
 sw_status check_prepared(const sw_plan *p, void *ws);
+// A named roctx range over the enclosing scope (no-op without the roctx
+// library; trace.cpp).
+class Range {
+public:
+    explicit Range(const char *name);
+    ~Range();
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+
+private:
+    bool active_ = false;
+};
 // Device address and size of the no-allocation batch's fixed descriptor table
 // on the current device (resolved once per device; k_points.hip).
 hipError_t static_batch_table(void **ptr, size_t *bytes);

@@ -290,3 +290,75 @@ def test_double_precision_contract():
     assert L.STATUS[st] in ("SW_ERR_STATE", "SW_ERR_ARG")
     _expect("SW_ERR_UNSUPPORTED", p64.set_tiling, 16, 4)
     assert p64.tiling["tx"] == 8
+
+
+def test_batch_tiling_contract():
+    lib = L.lib()
+
+    def batch_of(props):
+        arr = (ctypes.c_void_p * len(props))(*[p._plan.value for p in props])
+        h = ctypes.c_void_p()
+        assert L.STATUS[lib.sw_batch_create(len(props), arr, ctypes.byref(h))] == "SW_OK"
+        return h
+
+    def get(h):
+        t, bpc = L.Tiling(), ctypes.c_int32()
+        assert L.STATUS[lib.sw_batch_get_tiling(h, ctypes.byref(t), ctypes.byref(bpc))] == "SW_OK"
+        return (t.tx, t.nw, t.zc, t.nt, t.pf, bpc.value)
+
+    def put(h, cfg, bpc=0):
+        t = None if cfg is None else L.Tiling(*cfg)
+        return L.STATUS[lib.sw_batch_set_tiling(h, ctypes.byref(t) if t is not None else None, bpc)]
+
+    shots = [Propagator((30, 34, 40), (10.0,) * 3, 8, 1e-3, 5, nbl=4),
+             Propagator((26, 40, 30), (10.0,) * 3, 8, 1e-3, 5, nbl=4)]
+    h = batch_of(shots)
+    try:
+        assert get(h) == (16, 4, 64, 1, 1, 0)
+        assert put(h, (24, 8, 11, 0, 2, 0, 1, 0, 1), -1) == "SW_OK"
+        assert get(h) == (24, 8, 11, 0, 2, -1)
+        assert put(h, (8, 4, 0, 1, 1, 0, 1, 0, 1), 6) == "SW_OK"
+        assert get(h)[2:] == (64, 1, 1, 6)
+        assert put(h, (12, 4, 0, 1, 1, 0, 1, 0, 1)) == "SW_ERR_ARG"          # shape not instantiated
+        assert put(h, (16, 4, 0, 1, 3, 0, 1, 0, 1)) == "SW_ERR_ARG"          # prefetch depth
+        assert put(h, (16, 4, 0, 1, 1, 0, 1, 0, 1), -2) == "SW_ERR_ARG"      # grid option
+        assert put(h, (16, 4, 0, 1, 1, 1, 1, 0, 1)) == "SW_ERR_UNSUPPORTED"  # wave tiles
+        assert put(h, (16, 4, 0, 1, 1, 0, 2, 0, 1)) == "SW_ERR_UNSUPPORTED"  # two-step sweep
+        assert put(h, None) == "SW_OK"
+        assert get(h) == (16, 4, 64, 1, 1, 0)
+    finally:
+        lib.sw_batch_destroy(h)
+    h = batch_of([Propagator((30, 34), (10.0,) * 2, 8, 1e-3, 5, nbl=4)])
+    try:
+        assert get(h)[:2] == (1, 1)
+        assert put(h, (16, 4, 0, 1, 1, 0, 1, 0, 1)) == "SW_ERR_ARG"
+        assert put(h, None) == "SW_OK"
+        assert get(h)[:2] == (1, 1)
+    finally:
+        lib.sw_batch_destroy(h)
+
+
+def test_roctx_ranges_open_the_tracing_library():
+    # in a process without torch: the first enqueueing call (here refused for a
+    # NULL plan) opens the roctx library for its range; SW_ROCTX=0 keeps it closed
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys\n"
+        "lib = ctypes.CDLL(sys.argv[1])\n"
+        "maps = lambda: 'librocprofiler-sdk-roctx' in open('/proc/self/maps').read()\n"
+        "before = maps()\n"
+        "st = lib.sw_forward(None, None, None)\n"
+        "print(int(before), int(maps()), st)\n")
+    path = L.LIB_PATH
+    for env, want in ((None, "0 1"), ("0", "0 0")):
+        e = dict(os.environ)
+        e.pop("SW_ROCTX", None)
+        if env is not None:
+            e["SW_ROCTX"] = env
+        out = subprocess.run([sys.executable, "-c", code, path], capture_output=True, text=True, env=e,
+                             timeout=120)
+        assert out.returncode == 0, out.stderr
+        before_after, st = out.stdout.split()[:2], int(out.stdout.split()[2])
+        assert " ".join(before_after) == want, out.stdout
+        assert L.STATUS[st] == "SW_ERR_ARG"
