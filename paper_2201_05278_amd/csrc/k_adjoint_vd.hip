@@ -14,7 +14,10 @@
 //   x       = (dJ/dK + S / K^2) / b          (dJ/dc = fold(x) 2 dt^2 c)
 //   y       = dJ/dK K b - dJ/db b^2          (dJ/drho = fold(y))
 // with dJ/dK accumulated by the imaging stencil and M = K b.
+#include <algorithm>
+
 #include "device.h"
+#include "stencil_const.h"
 
 namespace sw {
 
@@ -88,8 +91,12 @@ struct FaceTileParams {
 // sums are read and written once for all pairs.  z differences come from
 // rotating register queues (2R planes, compile-time slots), x and y
 // differences from the plane staged in LDS with R - 1 nodes of halo below and
-// R above: the tile's own nodes from the queues, the halo from memory; off-grid
-// nodes read zero.
+// R above: the tile's own nodes from the queues, the halo from memory.
+// Buffer addressing as in the stencils: one descriptor per array over the
+// block's z window, 32-bit in-plane byte offsets fixed before the march (the
+// halo items of each thread included), off-grid x / y positions at an offset
+// past the descriptor (loads read zero, stores are dropped) and off-grid z
+// planes masked to zero.
 template <int R, int NDIM, int NW, int RPT, int NP>
 __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
 {
@@ -101,8 +108,12 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
     constexpr int NTH = 64 * NW;
     constexpr int NF = 2 * NP;                   // staged fields: phi and u of each pair
     constexpr int R0 = (NDIM == 3) ? HL : 0;     // LDS row of the tile's first row (2D: one row, no x halo)
+    constexpr int NXH = (NDIM == 3) ? (2 * R - 1) * LYC : 0;   // halo items: x-halo rows (all columns)
+    constexpr int NH = NXH + TX * (2 * R - 1);                  // and the y-halo columns of the tile's rows
+    constexpr int NHT = (NH + NTH - 1) / NTH;                   // halo items per thread
+    constexpr int kOut = 0x7ffffe00;
     static_assert(NDIM == 3 || (NW == 1 && RPT == 1), "2D tiles are one row");
-    __shared__ float sf[NF][LXR][LYC];
+    __shared__ float sf[NF][LXR * LYC + 1];      // element LXR * LYC: sink of idle halo items
     const Geom &g = P.g;
     const float *src[NF];
 #pragma unroll
@@ -117,10 +128,44 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
     const int y = y0 + lane;
     const int zb = zc * P.zc;
     const int ze = min(zb + P.zc, g.Z);
-    auto val = [&](const float *f, int z, int xx, int yy) -> float {
-        return (z >= 0 && z < g.Z && xx >= 0 && xx < g.X && yy >= 0 && yy < g.Y) ? f[elem(g, z, xx, yy)]
-                                                                              : 0.0f;
+    // windows: planes zw .. zt - 1 of the staged fields, zb .. ze - 1 of the face sums
+    const int zw = zb - R + 1, zt = ze + R;
+    const int64_t sz = int64_t(g.px) * g.py;
+    const int pb = int(sz) * 4;
+    const int64_t w0 = g.base + int64_t(zw) * sz, f0e = g.base + int64_t(zb) * sz;
+    __amdgpu_buffer_rsrc_t rs[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) rs[f] = buf_res(src[f] + w0, uint32_t(zt - zw) * uint32_t(pb));
+    const uint32_t fbytes = uint32_t(ze - zb) * uint32_t(pb);
+    const auto rf0 = buf_res(P.F[0] + f0e, fbytes);
+    const auto rf1 = buf_res(P.F[NDIM == 3 ? 1 : 0] + f0e, fbytes);
+    const auto rf2 = buf_res(P.F[2] + f0e, fbytes);
+    auto off = [&](int x, int yy) -> int {
+        return (x >= 0 && x < g.X && yy >= 0 && yy < g.Y) ? (g.xy0 + x * g.py + yy) * 4 : kOut;
     };
+    auto zmask = [&](int z) -> unsigned { return (z >= 0 && z < g.Z) ? ~0u : 0u; };
+    int ro[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) ro[i] = off(x0 + wave * RPT + i, y);
+    int ho[NHT], hl[NHT];
+#pragma unroll
+    for (int t = 0; t < NHT; ++t) {
+        const int e = threadIdx.x + t * NTH;
+        int row = 0, col = 0;
+        if (e < NXH) {                       // rows 0 .. HL - 1 and R0 + TX .. LXR - 1, every column
+            const int k = e / LYC;
+            col = e % LYC;
+            row = (k < HL) ? k : R0 + TX + (k - HL);
+        } else {                             // columns 0 .. HL - 1 and HL + 64 .. LYC - 1 of the tile's rows
+            const int e2 = e - NXH;
+            const int k = e2 % (2 * R - 1);
+            row = R0 + e2 / (2 * R - 1);
+            col = (k < HL) ? k : HL + 64 + (k - HL);
+        }
+        const bool ok = e < NH;
+        ho[t] = ok ? off((NDIM == 3) ? x0 - HL + row : 0, y0 - HL + col) : kOut;
+        hl[t] = ok ? row * LYC + col : LXR * LYC;
+    }
     // slot (s + k) % Q of field f, row i holds the value at z - R + 1 + k on step s (z = zz + s)
     float q[NF][RPT][Q];
 #pragma unroll
@@ -128,41 +173,36 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
-            for (int k = 0; k < Q - 1; ++k) q[f][i][k] = val(src[f], zb - R + 1 + k, x0 + wave * RPT + i, y);
+            for (int k = 0; k < Q - 1; ++k)
+                q[f][i][k] = keep_mask(buf_ld<0>(rs[f], ro[i], k * pb), zmask(zw + k));
     for (int zz = zb; zz < ze; zz += Q) {
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
             const int z = zz + s;
             if (z >= ze) break;
+            const int fo = (z - zb) * pb;
             // this plane's face sums are loaded first, so that they arrive
             // while the plane is staged
             float f0[RPT], f1[RPT], f2[RPT];
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const int x = x0 + wave * RPT + i;
-                const bool own = x < g.X && y < g.Y;
-                const int64_t o = own ? elem(g, z, x, y) : 0;
-                f0[i] = own ? P.F[0][o] : 0.0f;
-                f1[i] = (NDIM == 3 && own) ? P.F[1][o] : 0.0f;
-                f2[i] = own ? P.F[2][o] : 0.0f;
+                f0[i] = buf_ld<1>(rf0, ro[i], fo);
+                f1[i] = (NDIM == 3) ? buf_ld<1>(rf1, ro[i], fo) : 0.0f;
+                f2[i] = buf_ld<1>(rf2, ro[i], fo);
+                const unsigned m = zmask(z + R);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    q[f][i][(s + Q - 1) % Q] = val(src[f], z + R, x, y);
-                    sf[f][R0 + wave * RPT + i][HL + lane] = q[f][i][(s + R - 1) % Q];
+                    q[f][i][(s + Q - 1) % Q] = keep_mask(buf_ld<0>(rs[f], ro[i], (z + R - zw) * pb), m);
+                    sf[f][(R0 + wave * RPT + i) * LYC + HL + lane] = q[f][i][(s + R - 1) % Q];
                 }
             }
-            for (int e = threadIdx.x; e < LXR * LYC; e += NTH) {
-                const int i = e / LYC, j = e % LYC;
-                if (i >= R0 && i < R0 + TX && j >= HL && j < HL + 64) continue;   // the tile's own nodes
-                const int xx = (NDIM == 3) ? x0 - HL + i : 0;
-                const int yy = y0 - HL + j;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) sf[f][i][j] = val(src[f], z, xx, yy);
-            }
+            for (int t = 0; t < NHT; ++t)
+#pragma unroll
+                for (int f = 0; f < NF; ++f) sf[f][hl[t]] = buf_ld<0>(rs[f], ho[t], (z - zw) * pb);
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const int x = x0 + wave * RPT + i;
                 const int ci = R0 + wave * RPT + i, cj = HL + lane;
                 float a0 = f0[i], a1 = f1[i], a2 = f2[i];
 #pragma unroll
@@ -174,22 +214,19 @@ __global__ void __launch_bounds__(64 * NW) k_face_tile(FaceTileParams P)
                         dpz = fmaf(P.sz[l], q[fp][i][(s + R - 1 + l) % Q] - q[fp][i][(s + R - l) % Q], dpz);
                         duz = fmaf(P.sz[l], q[fu][i][(s + R - 1 + l) % Q] - q[fu][i][(s + R - l) % Q], duz);
                         if constexpr (NDIM == 3) {
-                            dpx = fmaf(P.sx[l], sf[fp][ci + l][cj] - sf[fp][ci - l + 1][cj], dpx);
-                            dux = fmaf(P.sx[l], sf[fu][ci + l][cj] - sf[fu][ci - l + 1][cj], dux);
+                            dpx = fmaf(P.sx[l], sf[fp][(ci + l) * LYC + cj] - sf[fp][(ci - l + 1) * LYC + cj], dpx);
+                            dux = fmaf(P.sx[l], sf[fu][(ci + l) * LYC + cj] - sf[fu][(ci - l + 1) * LYC + cj], dux);
                         }
-                        dpy = fmaf(P.sy[l], sf[fp][ci][cj + l] - sf[fp][ci][cj - l + 1], dpy);
-                        duy = fmaf(P.sy[l], sf[fu][ci][cj + l] - sf[fu][ci][cj - l + 1], duy);
+                        dpy = fmaf(P.sy[l], sf[fp][ci * LYC + cj + l] - sf[fp][ci * LYC + cj - l + 1], dpy);
+                        duy = fmaf(P.sy[l], sf[fu][ci * LYC + cj + l] - sf[fu][ci * LYC + cj - l + 1], duy);
                     }
                     a0 = fmaf(-dpz, duz, a0);
                     if constexpr (NDIM == 3) a1 = fmaf(-dpx, dux, a1);
                     a2 = fmaf(-dpy, duy, a2);
                 }
-                if (x < g.X && y < g.Y) {
-                    const int64_t o = elem(g, z, x, y);
-                    P.F[0][o] = a0;
-                    if constexpr (NDIM == 3) P.F[1][o] = a1;
-                    P.F[2][o] = a2;
-                }
+                buf_st<1>(a0, rf0, ro[i], fo);
+                if constexpr (NDIM == 3) buf_st<1>(a1, rf1, ro[i], fo);
+                buf_st<1>(a2, rf2, ro[i], fo);
             }
             __syncthreads();
         }
@@ -314,6 +351,11 @@ hipError_t launch_face_image(const Geom &g, int ndim, int r, const float *const 
     T.ntx = (g.X + tx - 1) / tx;
     T.nty = (g.Y + 63) / 64;
     T.zc = (ndim == 2) ? 16 : 32;
+    // a block's window (chunk plus 2r - 1 planes) stays below 2^31 bytes: 32-bit buffer offsets
+    const int64_t pbytes = int64_t(g.px) * g.py * 4;
+    const int64_t zmax = ((int64_t(1) << 31) - 1) / pbytes - (2 * r - 1);
+    if (zmax < 1) return hipErrorInvalidValue;
+    T.zc = int(std::min<int64_t>(T.zc, zmax));
     T.nzc = (g.Z + T.zc - 1) / T.zc;
     switch (r) {
     case 1: launch_face_tile<1>(ndim, np, T, s); break;
