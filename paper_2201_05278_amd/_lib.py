@@ -105,6 +105,7 @@ SIGNATURES = {
     "sw_adjoint": (c_int32, [c_void_p, ctypes.POINTER(AdjIO), c_void_p]),
     "sw_plan_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
     "sw_plan_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
+    "sw_plan_occupancy": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "sw_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "sw_batch_destroy": (c_int32, [c_void_p]),
     "sw_batch_layout": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),

@@ -1,5 +1,6 @@
 // C ABI of the propagator (declarations and contracts in include/simwave_hip.h).
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -109,6 +110,56 @@ int default_zc(const sw_plan *p, int tx, int64_t want, int ts)
     return std::max(zc, std::min(p->dims[0], 4 * p->r));
 }
 
+// Resident blocks per CU of the plan's 3D constant-density forward kernel for
+// tiling t (queried once per plan and tiling; 0 without a device).
+int resident_blocks(const sw_plan *p, const Tiling &t)
+{
+    const uint64_t key = (uint64_t(t.tx) << 40) | (uint64_t(t.nw) << 32) | (uint64_t(t.nt) << 24) |
+                         (uint64_t(t.pf) << 16) | (uint64_t(t.wt) << 12) | (uint64_t(t.ts) << 8) |
+                         uint64_t(t.occ & 0xff);
+    for (const auto &e : p->resident_cache)
+        if (e.first == key) return e.second;
+    int dev = 0, n = 0;
+    if (!p->ncu)
+        p->ncu = (hipGetDevice(&dev) == hipSuccess &&
+                  hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+                     ? n
+                     : -1;
+    const int r = p->ncu > 0 ? const_resident_blocks(p->r, t) : 0;
+    p->resident_cache.emplace_back(key, r);
+    return r;
+}
+
+// z-chunk length from whole rounds of resident blocks: a launch of B blocks
+// runs in about ceil(B / resident) rounds, each as long as one block's march
+// over its chunk and the 2R planes around it, so the chunk with the least
+// rounds x (zc + 2R) is taken (ties: the shorter chunk), among chunks of
+// 4R .. kMaxChunk planes that make at least kMinRounds rounds (launches of
+// fewer, longer blocks ran up to 14% slower on a 400^3 grid whatever their
+// rounds); 0 if no chunk qualifies.
+constexpr int kMaxChunk = 100;
+constexpr int kMinRounds = 3;
+int rounds_zc(const sw_plan *p, const Tiling &t, int64_t resident)
+{
+    const int Z = p->dims[0];
+    const int64_t tiles = int64_t((p->dims[1] + t.tx - 1) / t.tx) * ((p->dims[2] + 63) / 64);
+    int best = 0;
+    int64_t best_cost = std::numeric_limits<int64_t>::max();
+    for (int nzc = 1; nzc <= Z; ++nzc) {
+        const int zc = (Z + nzc - 1) / nzc;
+        if (zc > kMaxChunk) continue;
+        if (zc < 4 * p->r) break;
+        const int64_t blocks = tiles * ((Z + zc - 1) / zc);
+        if (blocks < kMinRounds * resident) continue;
+        const int64_t cost = ((blocks + resident - 1) / resident) * (zc + 2 * p->r);
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+    }
+    return best;
+}
+
 // Default constant-density block tile and resident-block cap by radius, from a
 // sweep of the forward stencil at 592^3 over space orders 2 .. 16: short
 // stencils stream fastest with 8x4 tiles held to 4 blocks per CU (fewer z
@@ -172,6 +223,16 @@ Tiling choose_tiling(const sw_plan *p)
     t.pf = p->tile_pf ? p->tile_pf : kDefaultPF;
     // the occupancy cap applies to single-step block tiles
     t.occ = (t.wt || t.ts == 2) ? 0 : (p->tile_occ < 0 ? def_occ : p->tile_occ);
+    // 3D constant-density block tiles on a device: chunks by rounds of resident
+    // blocks (the fixed wave target where no chunk makes enough rounds)
+    if (!p->tile_zc && p->ndim == 3 && p->prob.scheme == SW_CONST && p->prob.dtype == SW_F32 && !t.wt &&
+        t.ts == 1) {
+        const int res = resident_blocks(p, t);
+        if (res > 0) {
+            const int zc = rounds_zc(p, t, int64_t(res) * p->ncu);
+            if (zc > 0) t.zc = zc;
+        }
+    }
     // block order: y tiles fastest unless x tiles fastest is asked (block tiles only)
     t.xfast = (t.wt || t.ts == 2) ? 0 : (p->tile_order == 2 ? 1 : 0);
     return t;
@@ -476,6 +537,22 @@ sw_status sw_plan_get_tiling(const sw_plan *p, sw_tiling *out)
     if (!p || !out) return fail(SW_ERR_ARG, "NULL argument");
     const Tiling t = choose_tiling(p);
     *out = sw_tiling{t.tx, t.nw, t.zc, t.nt, t.pf, t.wt, t.ts, t.occ, t.xfast ? 2 : 1};
+    return SW_OK;
+}
+
+sw_status sw_plan_occupancy(const sw_plan *p, int32_t *blocks_per_cu, int32_t *cus)
+{
+    set_error("");
+    if (!p || !blocks_per_cu || !cus) return fail(SW_ERR_ARG, "NULL argument");
+    *blocks_per_cu = 0;
+    *cus = 0;
+    const Tiling t = choose_tiling(p);
+    if (p->ndim != 3 || p->prob.scheme != SW_CONST || p->prob.dtype != SW_F32 || t.wt || t.ts != 1) return SW_OK;
+    const int n = resident_blocks(p, t);
+    if (n > 0 && p->ncu > 0) {
+        *blocks_per_cu = n;
+        *cus = p->ncu;
+    }
     return SW_OK;
 }
 

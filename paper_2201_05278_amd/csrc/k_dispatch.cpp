@@ -34,6 +34,17 @@ hipError_t launch_const_r10(int, int, const Tiling &, StencilParams &, hipStream
 hipError_t launch_batch_r10(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
 hipError_t launch_vd_r10(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 
+int const_resident_r1(const Tiling &);
+int const_resident_r2(const Tiling &);
+int const_resident_r3(const Tiling &);
+int const_resident_r4(const Tiling &);
+int const_resident_r5(const Tiling &);
+int const_resident_r6(const Tiling &);
+int const_resident_r7(const Tiling &);
+int const_resident_r8(const Tiling &);
+int const_resident_r9(const Tiling &);
+int const_resident_r10(const Tiling &);
+
 hipError_t launch_tb_r1(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
 hipError_t launch_tb_r2(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
 hipError_t launch_tb_r3(const Tiling &, StencilParams &, const TwoStepParams &, hipStream_t);
@@ -57,6 +68,23 @@ hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParam
     case 9: return launch_const_r9(ndim, mode, t, P, s);
     case 10: return launch_const_r10(ndim, mode, t, P, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+int const_resident_blocks(int r, const Tiling &t)
+{
+    switch (r) {
+    case 1: return const_resident_r1(t);
+    case 2: return const_resident_r2(t);
+    case 3: return const_resident_r3(t);
+    case 4: return const_resident_r4(t);
+    case 5: return const_resident_r5(t);
+    case 6: return const_resident_r6(t);
+    case 7: return const_resident_r7(t);
+    case 8: return const_resident_r8(t);
+    case 9: return const_resident_r9(t);
+    case 10: return const_resident_r10(t);
+    default: return 0;
     }
 }
 

@@ -10,6 +10,8 @@ hipError_t launch_const_r4(int ndim, int mode, const Tiling &t, StencilParams &P
     return launch_const_radius<4>(ndim, mode, t, P, s);
 }
 
+int const_resident_r4(const Tiling &t) { return const_resident_radius<4>(t); }
+
 hipError_t launch_batch_r4(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
                             int nshots, int parity, int nblocks, hipStream_t s)
 {

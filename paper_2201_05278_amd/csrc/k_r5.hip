@@ -10,6 +10,8 @@ hipError_t launch_const_r5(int ndim, int mode, const Tiling &t, StencilParams &P
     return launch_const_radius<5>(ndim, mode, t, P, s);
 }
 
+int const_resident_r5(const Tiling &t) { return const_resident_radius<5>(t); }
+
 hipError_t launch_batch_r5(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
                             int nshots, int parity, int nblocks, hipStream_t s)
 {

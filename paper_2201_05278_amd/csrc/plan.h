@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/simwave_hip.h"
@@ -98,6 +99,10 @@ struct sw_plan {
     // bumped by every call that changes what a captured launch bakes in
     // (point tables and counts, model, tiling); part of the graph keys
     uint64_t generation = 1;
+    // resident blocks per CU of the constant-density block-tile kernels, by
+    // tiling key (queried once per kernel), and the device's CU count
+    mutable std::vector<std::pair<uint64_t, int>> resident_cache;
+    mutable int ncu = 0;
     // cached HIP graph of a forward run, captured on a private stream
     void *graph_exec = nullptr;
     void *capture_stream = nullptr;

@@ -619,6 +619,35 @@ hipError_t launch_const_v(int ndim, int mode, const Tiling &t, StencilParams &P,
     return hipErrorInvalidValue;
 }
 
+// Resident blocks per CU of the forward block-tile kernel of a 3D tiling (with
+// its occupancy cap), from the runtime's occupancy calculator; 0 if unknown.
+template <int R, int TX, int NW, int NT, int PF>
+int const_resident_shape(int occ)
+{
+    constexpr auto kern = k_const<R, 3, TX, NW, MODE_FWD, NT, PF>;
+    const unsigned pad = occ ? occ_pad_bytes(occ, static_lds_of<kern>()) : 0u;
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 64 * NW, pad) == hipSuccess ? n : 0;
+}
+
+template <int R, int NT, int PF>
+int const_resident_v(const Tiling &t)
+{
+#define SW_X(TXV, NWV) \
+    if (t.tx == TXV && t.nw == NWV) return const_resident_shape<R, TXV, NWV, NT, PF>(t.occ);
+    SW_CONST_SHAPES(SW_X)
+#undef SW_X
+    return 0;
+}
+
+template <int R>
+int const_resident_radius(const Tiling &t)
+{
+    if (t.wt || t.ts == 2) return 0;
+    if (t.pf == 2) return t.nt ? const_resident_v<R, 1, 2>(t) : const_resident_v<R, 0, 2>(t);
+    return t.nt ? const_resident_v<R, 1, 1>(t) : const_resident_v<R, 0, 1>(t);
+}
+
 template <int R>
 hipError_t launch_const_radius(int ndim, int mode, const Tiling &t, StencilParams &P, hipStream_t s)
 {

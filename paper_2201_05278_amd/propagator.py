@@ -251,6 +251,14 @@ class Propagator:
         L.check("sw_plan_get_tiling", L.lib().sw_plan_get_tiling(self._plan, ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in L.Tiling._fields_}
 
+    @property
+    def occupancy(self):
+        """(resident blocks per CU, CUs) of the stencil kernel under the current
+        tiling: 3D constant-density block tiles on a device, else (0, 0)."""
+        n, c = ctypes.c_int32(), ctypes.c_int32()
+        L.check("sw_plan_occupancy", L.lib().sw_plan_occupancy(self._plan, ctypes.byref(n), ctypes.byref(c)))
+        return n.value, c.value
+
     def autotune(self, cache_path=None):
         """Time candidate tilings on scratch buffers and keep the fastest (or
         reuse the choice cached in the JSON file cache_path)."""

@@ -179,3 +179,41 @@ def test_capped_kernel_first_launched_inside_graph_capture():
         assert torch.equal(e.traces, r.traces)
         assert torch.equal(prop.grid_view(e.fields[e.current]), prop.grid_view(r.fields[r.current]))
     prop.set_tiling()
+
+
+@pytest.mark.parametrize("n,nbl,so", [((512,) * 3, 40, 8), ((207, 801, 801), 0, 8), ((207, 801, 801), 0, 4),
+                                      ((512,) * 3, 40, 12), ((60, 70, 80), 4, 8)])
+def test_default_chunk_follows_resident_rounds(n, nbl, so):
+    # the default z chunk of 3D constant-density block tiles, recomputed from
+    # its stated rule and the kernel's resident blocks (plans only, no device
+    # memory): the chunk of 4R .. 100 planes with the fewest
+    # ceil(blocks / resident) * (zc + 2R), ties to the shorter chunk, among
+    # chunks making at least three rounds; else the fixed wave target
+    import math
+    prop = Propagator(n, (10.0,) * 3, so, 1e-4, 5, nbl=nbl)
+    t = prop.tiling
+    res, cus = prop.occupancy
+    print(f"case: default chunk {n} + {nbl} SO{so}: tiling {t}, resident {res} x {cus}", flush=True)
+    assert res > 0 and cus > 0
+    Z, X, Y = [k + 2 * nbl for k in n]
+    r = so // 2
+    tiles = math.ceil(X / t["tx"]) * math.ceil(Y / 64)
+    cap = res * cus
+    best, best_cost = None, None
+    for nzc in range(1, Z + 1):
+        zc = math.ceil(Z / nzc)
+        if zc > 100:
+            continue
+        if zc < 4 * r:
+            break
+        blocks = tiles * math.ceil(Z / zc)
+        if blocks < 3 * cap:
+            continue
+        cost = math.ceil(blocks / cap) * (zc + 2 * r)
+        if best_cost is None or cost <= best_cost:
+            best, best_cost = zc, cost
+    if best is None:
+        want = 16000 // t["nw"]
+        nzc = max(1, math.ceil(want / tiles))
+        best = min(74, Z, max(math.ceil(Z / nzc), min(Z, 4 * r)))
+    assert t["zc"] == best
