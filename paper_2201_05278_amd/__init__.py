@@ -7,5 +7,5 @@ C ABI declared in include/simwave_hip.h.  This package is the thin Python
 binding over it.
 """
 from .propagator import (Propagator, ForwardResult, AcousticForward, AcousticForwardVD, Batch,  # noqa: F401
-                         critical_dt, steps_for, ricker)
+                         critical_dt, steps_for, ricker, forward, remove_nbl)
 from ._lib import SimwaveError, lib  # noqa: F401

@@ -51,6 +51,45 @@ def ricker(f_peak, dt, nsteps, t0=0.0):
     return torch.tensor(list(buf)[:nsteps], dtype=torch.float32)
 
 
+def remove_nbl(prop, grid):
+    """Physical part of an extended-grid array of plan `prop` (the paper's
+    remove_nbl)."""
+    return prop.physical_view(grid)
+
+
+def forward(vel, h, space_order, dt, nsteps, src, rec, wavelet=None, f_peak=10.0, rho=None, scheme="const",
+            nbl=0, bc=None, src_interp="hicks", rec_interp="hicks", radius=4, saving_stride=0, cmax=None,
+            dtype="float32", alpha=0.001, power=3.0, device="cuda"):
+    """A whole forward run in one call (the paper's solver forward): plan,
+    sources and receivers (coordinates in metres), model (physical-grid
+    velocity and, for the variable-density schemes, density), nsteps steps.
+    wavelet: (nsteps, nsrc) or (nsteps,) samples; None: a Ricker wavelet of
+    peak frequency f_peak at every source.  Returns (traces (nsteps, nrec),
+    the last wavefield on the physical grid, the snapshots taken every
+    saving_stride steps on the physical grid, or None)."""
+    import numpy as np
+    vel = torch.as_tensor(vel)
+    n = tuple(vel.shape)
+    prop = Propagator(n, h, space_order, dt, nsteps, scheme=scheme, nbl=nbl, alpha=alpha, power=power,
+                      device=device, bc=bc, dtype=dtype)
+    src = np.asarray(src, dtype=np.float64).reshape(-1, len(n))
+    prop.set_sources(src, src_interp, radius)
+    prop.set_receivers(np.asarray(rec, dtype=np.float64).reshape(-1, len(n)), rec_interp, radius)
+    prop.prepare(vel.to(prop.device), None if rho is None else torch.as_tensor(rho).to(prop.device), cmax=cmax)
+    if wavelet is None:
+        wavelet = ricker(f_peak, dt, nsteps).reshape(-1, 1).repeat(1, len(src))
+    wavelet = torch.as_tensor(wavelet).reshape(nsteps, -1)
+    if wavelet.shape[1] == 1 and len(src) > 1:
+        wavelet = wavelet.repeat(1, len(src))
+    res = prop.forward(wavelet.to(prop.device), saving_stride=saving_stride)
+    last = prop.physical_view(prop.grid_view(res.fields[res.current])).clone()
+    snaps = None
+    if res.snaps is not None:
+        snaps = res.snaps[(slice(None),) + tuple(
+            slice(int(prop.prob.nbl[i][0]), int(prop.prob.nbl[i][0]) + n[i]) for i in range(len(n)))].clone()
+    return res.traces, last, snaps
+
+
 @dataclass
 class ForwardResult:
     traces: torch.Tensor        # (nsteps, nrec)

@@ -217,3 +217,29 @@ def test_default_chunk_follows_resident_rounds(n, nbl, so):
         nzc = max(1, math.ceil(want / tiles))
         best = min(74, Z, max(math.ceil(Z / nzc), min(Z, 4 * r)))
     assert t["zc"] == best
+
+
+def test_one_call_forward_matches_oracle_and_plan_path():
+    # the one-call forward: traces, last field and snapshots on the physical
+    # grid against the oracle, and bitwise against the plan-level run
+    from paper_2201_05278_amd import forward, remove_nbl
+    n = (60, 84)
+    vel = workloads.smooth_random(n, 9, factor=6)
+    h = (10.0, 12.5)
+    src = np.array([[123.4, 501.0]])
+    rec = np.array([[30.0, 12.5 * k] for k in range(0, 84, 3)])
+    nbl = ((3, 11), (7, 9))
+    print("case: one-call forward, 2D smooth model, uneven layer, snapshots", flush=True)
+    ref, res, prop, wav = run_pair(n, h, 8, nbl, 160, vel, src, rec, f=18.0, saving_stride=40)
+    tr, last, snaps = forward(vel, h, 8, prop.dt, 160, src, rec, wavelet=wav.astype(np.float32),
+                              nbl=[list(p) for p in nbl], saving_stride=40)
+    torch.cuda.synchronize()
+    assert torch.equal(tr, res.traces)
+    phys = remove_nbl(prop, prop.grid_view(res.fields[res.current]))
+    assert torch.equal(last, phys)
+    assert tuple(last.shape) == n and tuple(snaps.shape) == (4,) + n
+    for k in range(4):
+        assert torch.equal(snaps[k], remove_nbl(prop, res.snaps[k]))
+    assert_traces(tr, ref.traces)
+    full = ref.p[nbl[0][0]:nbl[0][0] + n[0], nbl[1][0]:nbl[1][0] + n[1]]
+    assert rel(last.double().cpu().numpy(), full) < TOL
