@@ -21,6 +21,11 @@ Cases:
                     and column stored)
   batch_shots       the smallest and the largest of the 64 uneven batch
                     shots, SO8, 400 steps (every 4th receiver row and column)
+  smooth200_stag    200^3 + layer, smooth random velocity, Gardner density,
+                    staggered variable density, SO8, 400 steps (the oracle's
+                    staggered operator runs at about 0.0025 Gpts/s here, so
+                    the headline 512^3 grid is out of its reach), trilinear
+                    source / receivers (every 10th row and column stored)
   gradient320       320^3 + layer layered + N(0, 50^2) model, 2 of the 8
                     shots, SO8, 300 steps, L2 misfit against data of the
                     unperturbed layered model; velocity gradient summed over
@@ -80,6 +85,18 @@ def case_smooth512_const():
     subset = grid_subset(nside, 16)
     return {"dt": dt, "nsteps": SMOOTH_STEPS, "subset": subset,
             "traces": _traces(wl, "const", dt, SMOOTH_STEPS, subset)}
+
+
+STAG_STEPS = 400
+
+
+def case_smooth200_stag():
+    wl = workloads.smooth_3d(n=200, nsteps=STAG_STEPS, scheme="vd_staggered")
+    dt = workloads.CFL_FRACTION * oracle.coeffs.critical_dt(wl.h, wl.space_order, wl.cmax)
+    nside = int(round(np.sqrt(len(wl.rec))))
+    subset = grid_subset(nside, 10)
+    return {"dt": dt, "nsteps": STAG_STEPS, "subset": subset,
+            "traces": _traces(wl, "vd_staggered", dt, STAG_STEPS, subset)}
 
 
 def batch_pick(shots):
