@@ -349,7 +349,7 @@ typedef struct sw_tiling {
 /* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan. */
 sw_status sw_plan_set_tiling(sw_plan *plan, const sw_tiling *t);
 /* The tiling the plan's stencil launches use (defaults resolved).  For 3D
- * constant-density block tiles in single precision on a device, the default
+ * block tiles in single precision on a device (every scheme), the default
  * z chunk is the one with the fewest whole rounds of resident blocks times
  * planes per block (chunks of 4r .. 100 planes making at least three rounds);
  * elsewhere (and without a device, or where no chunk qualifies) about 16000
@@ -357,8 +357,8 @@ sw_status sw_plan_set_tiling(sw_plan *plan, const sw_tiling *t);
 sw_status sw_plan_get_tiling(const sw_plan *plan, sw_tiling *out);
 /* Resident blocks per compute unit of the plan's stencil kernel under its
  * current tiling (the runtime's occupancy calculator) and the device's
- * compute units: set for 3D constant-density block tiles in single
- * precision, 0 and 0 otherwise or without a device. */
+ * compute units: set for 3D block tiles in single precision (every
+ * scheme), 0 and 0 otherwise or without a device. */
 sw_status sw_plan_occupancy(const sw_plan *plan, int32_t *blocks_per_cu, int32_t *cus);
 
 /* ---- batched shots and autotuning --------------------------------------- */

@@ -110,8 +110,8 @@ int default_zc(const sw_plan *p, int tx, int64_t want, int ts)
     return std::max(zc, std::min(p->dims[0], 4 * p->r));
 }
 
-// Resident blocks per CU of the plan's 3D constant-density forward kernel for
-// tiling t (queried once per plan and tiling; 0 without a device).
+// Resident blocks per CU of the plan's 3D forward kernel for tiling t
+// (queried once per plan and tiling; 0 without a device).
 int resident_blocks(const sw_plan *p, const Tiling &t)
 {
     const uint64_t key = (uint64_t(t.tx) << 40) | (uint64_t(t.nw) << 32) | (uint64_t(t.nt) << 24) |
@@ -125,7 +125,9 @@ int resident_blocks(const sw_plan *p, const Tiling &t)
                   hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
                      ? n
                      : -1;
-    const int r = p->ncu > 0 ? const_resident_blocks(p->r, t) : 0;
+    const int r = p->ncu <= 0                    ? 0
+                  : p->prob.scheme == SW_CONST ? const_resident_blocks(p->r, t)
+                                               : vd_resident_blocks(p->prob.scheme, p->r, t);
     p->resident_cache.emplace_back(key, r);
     return r;
 }
@@ -223,10 +225,9 @@ Tiling choose_tiling(const sw_plan *p)
     t.pf = p->tile_pf ? p->tile_pf : kDefaultPF;
     // the occupancy cap applies to single-step block tiles
     t.occ = (t.wt || t.ts == 2) ? 0 : (p->tile_occ < 0 ? def_occ : p->tile_occ);
-    // 3D constant-density block tiles on a device: chunks by rounds of resident
-    // blocks (the fixed wave target where no chunk makes enough rounds)
-    if (!p->tile_zc && p->ndim == 3 && p->prob.scheme == SW_CONST && p->prob.dtype == SW_F32 && !t.wt &&
-        t.ts == 1) {
+    // 3D block tiles in single precision on a device: chunks by rounds of
+    // resident blocks (the fixed wave target where no chunk makes enough rounds)
+    if (!p->tile_zc && p->ndim == 3 && p->prob.dtype == SW_F32 && !t.wt && t.ts == 1) {
         const int res = resident_blocks(p, t);
         if (res > 0) {
             const int zc = rounds_zc(p, t, int64_t(res) * p->ncu);
@@ -554,7 +555,7 @@ sw_status sw_plan_occupancy(const sw_plan *p, int32_t *blocks_per_cu, int32_t *c
     *blocks_per_cu = 0;
     *cus = 0;
     const Tiling t = choose_tiling(p);
-    if (p->ndim != 3 || p->prob.scheme != SW_CONST || p->prob.dtype != SW_F32 || t.wt || t.ts != 1) return SW_OK;
+    if (p->ndim != 3 || p->prob.dtype != SW_F32 || t.wt || t.ts != 1) return SW_OK;
     const int n = resident_blocks(p, t);
     if (n > 0 && p->ncu > 0) {
         *blocks_per_cu = n;

@@ -161,6 +161,9 @@ hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParam
 // Resident blocks per CU of the 3D constant-density forward block-tile kernel
 // of tiling t at radius r (0: wave tiles, two-step sweeps, or no device).
 int const_resident_blocks(int r, const Tiling &t);
+// The same for the 3D variable-density forward kernels (scheme 1 staggered,
+// 2 centred).
+int vd_resident_blocks(int scheme, int r, const Tiling &t);
 hipError_t launch_const_two(int r, const Tiling &t, StencilParams &P, const TwoStepParams &T, hipStream_t s);
 hipError_t launch_vd(int scheme, int mode, int r, int ndim, const Tiling &t, StencilParams &P, hipStream_t s);
 

@@ -34,6 +34,16 @@ hipError_t launch_const_r10(int, int, const Tiling &, StencilParams &, hipStream
 hipError_t launch_batch_r10(int, const Tiling &, const StencilParams *, const int *, int, int, int, hipStream_t);
 hipError_t launch_vd_r10(int, int, int, const Tiling &, StencilParams &, hipStream_t);
 
+int vd_resident_r1(int, const Tiling &);
+int vd_resident_r2(int, const Tiling &);
+int vd_resident_r3(int, const Tiling &);
+int vd_resident_r4(int, const Tiling &);
+int vd_resident_r5(int, const Tiling &);
+int vd_resident_r6(int, const Tiling &);
+int vd_resident_r7(int, const Tiling &);
+int vd_resident_r8(int, const Tiling &);
+int vd_resident_r9(int, const Tiling &);
+int vd_resident_r10(int, const Tiling &);
 int const_resident_r1(const Tiling &);
 int const_resident_r2(const Tiling &);
 int const_resident_r3(const Tiling &);
@@ -68,6 +78,23 @@ hipError_t launch_const(int r, int ndim, int mode, const Tiling &t, StencilParam
     case 9: return launch_const_r9(ndim, mode, t, P, s);
     case 10: return launch_const_r10(ndim, mode, t, P, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+int vd_resident_blocks(int scheme, int r, const Tiling &t)
+{
+    switch (r) {
+    case 1: return vd_resident_r1(scheme, t);
+    case 2: return vd_resident_r2(scheme, t);
+    case 3: return vd_resident_r3(scheme, t);
+    case 4: return vd_resident_r4(scheme, t);
+    case 5: return vd_resident_r5(scheme, t);
+    case 6: return vd_resident_r6(scheme, t);
+    case 7: return vd_resident_r7(scheme, t);
+    case 8: return vd_resident_r8(scheme, t);
+    case 9: return vd_resident_r9(scheme, t);
+    case 10: return vd_resident_r10(scheme, t);
+    default: return 0;
     }
 }
 

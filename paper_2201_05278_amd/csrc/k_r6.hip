@@ -12,6 +12,8 @@ hipError_t launch_const_r6(int ndim, int mode, const Tiling &t, StencilParams &P
 
 int const_resident_r6(const Tiling &t) { return const_resident_radius<6>(t); }
 
+int vd_resident_r6(int scheme, const Tiling &t) { return vd_resident_radius<6>(scheme, t); }
+
 hipError_t launch_batch_r6(int ndim, const Tiling &t, const StencilParams *shots, const int *tile_start,
                             int nshots, int parity, int nblocks, hipStream_t s)
 {

@@ -627,6 +627,35 @@ hipError_t launch_vd_nt(int scheme, int mode, int ndim, const Tiling &t, Stencil
     return hipErrorInvalidValue;
 }
 
+// Resident blocks per CU of the 3D forward kernel of a scheme (1 staggered,
+// else centred) and tiling, from the runtime's occupancy calculator; 0 if
+// unknown.
+template <auto KERN>
+int resident_of(int nw, int occ)
+{
+    const unsigned pad = occ ? occ_pad_bytes(occ, static_lds_of<KERN>()) : 0u;
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, KERN, 64 * nw, pad) == hipSuccess ? n : 0;
+}
+
+template <int R, int NT>
+int vd_resident_nt(int scheme, const Tiling &t)
+{
+#define SW_X(TXV, NWV)                                                                     \
+    if (t.tx == TXV && t.nw == NWV)                                                        \
+        return scheme == 1 ? resident_of<k_stag<R, 3, TXV, NWV, NT, MODE_FWD>>(NWV, t.occ) \
+                           : resident_of<k_cent<R, 3, TXV, NWV, NT>>(NWV, t.occ);
+    SW_VD_SHAPES(SW_X)
+#undef SW_X
+    return 0;
+}
+
+template <int R>
+int vd_resident_radius(int scheme, const Tiling &t)
+{
+    return t.nt ? vd_resident_nt<R, 1>(scheme, t) : vd_resident_nt<R, 0>(scheme, t);
+}
+
 template <int R>
 hipError_t launch_vd_radius(int scheme, int mode, int ndim, const Tiling &t, StencilParams &P, hipStream_t s)
 {
