@@ -162,6 +162,31 @@ int rounds_zc(const sw_plan *p, const Tiling &t, int64_t resident)
     return best;
 }
 
+// Default variable-density block tile by radius, from a sweep of the forward
+// stencils at 592^3 over SO 4 .. 20 (all shapes in one process): the
+// staggered kernel keeps 8x4 tiles up to radius 7 and needs fewer registers
+// per thread beyond (16x8 at radius 8: 2.90 against 6.69 ms; 8x8 at 9 and
+// 10: 4.67 against 16.3 ms at SO20); the centred kernel takes 8x4 at radius
+// 1 .. 2 and 9 .. 10, 16x8 at 3 .. 4, 8x8 at 5 .. 8.
+void vd_default(int scheme, int r, int &tx, int &nw)
+{
+    if (scheme == SW_VD_STAGGERED) {
+        tx = (r == 8) ? 16 : 8;
+        nw = (r <= 7) ? 4 : 8;
+        return;
+    }
+    if (r <= 2 || r >= 9) {
+        tx = 8;
+        nw = 4;
+    } else if (r <= 4) {
+        tx = 16;
+        nw = 8;
+    } else {
+        tx = 8;
+        nw = 8;
+    }
+}
+
 // Default constant-density block tile and resident-block cap by radius, from a
 // sweep of the forward stencil at 592^3 over space orders 2 .. 16: short
 // stencils stream fastest with 8x4 tiles held to 4 blocks per CU (fewer z
@@ -189,10 +214,12 @@ Tiling choose_tiling(const sw_plan *p)
         t.tx = kTile64X;
         t.nw = kTile64W;
     } else if (p->prob.scheme != SW_CONST) {
-        // variable-density kernels: 8x4 staggered, 16x8 centred (tiling sweep, 592^3 SO8)
-        const bool stag = p->prob.scheme == SW_VD_STAGGERED;
-        t.tx = p->tile_tx ? p->tile_tx : (stag ? 8 : 16);
-        t.nw = p->tile_tx ? p->tile_nw : (stag ? 4 : 8);
+        if (p->tile_tx) {
+            t.tx = p->tile_tx;
+            t.nw = p->tile_nw;
+        } else {
+            vd_default(p->prob.scheme, p->r, t.tx, t.nw);
+        }
     } else if (p->tile_tx) {
         t.tx = p->tile_tx;
         t.nw = p->tile_nw;

@@ -260,6 +260,20 @@ def test_occupancy_cap_and_default_tiles():
     assert vd.tiling["occ"] == 5
 
 
+def test_variable_density_default_tiles():
+    # default tile by scheme and order (measured per order)
+    expect = {("vd_staggered", 4): (8, 4), ("vd_staggered", 8): (8, 4), ("vd_staggered", 14): (8, 4),
+              ("vd_staggered", 16): (16, 8), ("vd_staggered", 18): (8, 8), ("vd_staggered", 20): (8, 8),
+              ("vd_centred", 4): (8, 4), ("vd_centred", 8): (16, 8), ("vd_centred", 12): (8, 8),
+              ("vd_centred", 16): (8, 8), ("vd_centred", 20): (8, 4)}
+    for (scheme, so), (tx, nw) in expect.items():
+        t = Propagator((40, 40, 40), (10.0,) * 3, so, 1e-4, 5, nbl=4, scheme=scheme).tiling
+        assert (t["tx"], t["nw"]) == (tx, nw), (scheme, so)
+    prop = Propagator((40, 40, 40), (10.0,) * 3, 16, 1e-4, 5, nbl=4, scheme="vd_staggered")
+    prop.set_tiling(8, 4)
+    assert (prop.tiling["tx"], prop.tiling["nw"]) == (8, 4)
+
+
 def test_adjoint_scheme_contract():
     # the centred variable-density operator is not symmetric: no adjoint for it;
     # the staggered one is (it then needs a prepared plan like any other)
