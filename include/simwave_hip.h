@@ -346,7 +346,10 @@ typedef struct sw_tiling {
     int32_t tx, nw, zc, nt, pf, wt, ts, occ, order;
 } sw_tiling;
 
-/* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan. */
+/* Set (t != NULL) or reset to the defaults (t == NULL) the tiling of a plan.
+ * SW_F64 plans take a tile shape (8x8, 16x8, 8x4 or 24x8 in 3D) and a z chunk
+ * only: wave tiles, two-step sweeps and occupancy caps are refused, and the
+ * cache policy, prefetch depth and block order are ignored. */
 sw_status sw_plan_set_tiling(sw_plan *plan, const sw_tiling *t);
 /* The tiling the plan's stencil launches use (defaults resolved).  For 3D
  * block tiles in single precision on a device (every scheme), the default

@@ -211,8 +211,8 @@ Tiling choose_tiling(const sw_plan *p)
         t.tx = 1;
         t.nw = 1;
     } else if (p->prob.dtype == SW_F64) {
-        t.tx = kTile64X;
-        t.nw = kTile64W;
+        t.tx = p->tile_tx ? p->tile_tx : kTile64X;
+        t.nw = p->tile_tx ? p->tile_nw : f64_default_nw(p->r);
     } else if (p->prob.scheme != SW_CONST) {
         if (p->tile_tx) {
             t.tx = p->tile_tx;
@@ -520,8 +520,23 @@ sw_status sw_plan_set_tiling(sw_plan *p, const sw_tiling *t)
 {
     set_error("");
     if (!p) return fail(SW_ERR_ARG, "plan is NULL");
-    if (p->prob.dtype == SW_F64 && t)
-        return fail(SW_ERR_UNSUPPORTED, "double-precision plans use their fixed tile shape");
+    if (p->prob.dtype == SW_F64 && t) {
+        // double precision: a tile shape and a z chunk (one cache policy and
+        // prefetch depth, no wave tiles, two-step sweeps or occupancy caps)
+        if (t->wt || t->ts == 2 || t->occ > 0)
+            return fail(SW_ERR_UNSUPPORTED, "double-precision plans take a tile shape and a z chunk only");
+        if (t->zc < 0) return fail(SW_ERR_ARG, "zc must be >= 0");
+        if ((t->tx || t->nw) && (p->ndim != 3 || !f64_shape_ok(t->tx, t->nw)))
+            return fail(SW_ERR_UNSUPPORTED, "tile shape not provided in double precision");
+        p->tile_tx = t->tx;
+        p->tile_nw = t->nw;
+        p->tile_zc = t->zc;
+        if (p->graph_exec) {
+            (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
+            p->graph_exec = nullptr;
+        }
+        return SW_OK;
+    }
     sw_tiling d{0, 0, 0, -1, 0, 0, 0, -1, 0};
     if (t) d = *t;
     if (d.order < 0 || d.order > 2) return fail(SW_ERR_ARG, "order must be 0 (default), 1 or 2");

@@ -138,6 +138,7 @@ sw_status sw_forward_f64(sw_plan *p, const sw_fwd64_io *io, void *stream)
     void *ws = io->workspace;
     StencilParamsT<double> P;
     fill_params64(p, ws, P);
+    const Tiling t = choose_tiling(p);
     const PointTable64 src = table64(p->src, p->ws.src, ws);
     const PointTable64 rec = table64(p->rec, p->ws.rec, ws);
     const Geom g = make_geom(p);
@@ -152,7 +153,7 @@ sw_status sw_forward_f64(sw_plan *p, const sw_fwd64_io *io, void *stream)
         if (p->mirror) SW_HIP(launch_ghost64(g, p->bcm, p->ghost, cur, s));
         P.cur = cur;
         P.nxt = nxt;
-        SW_HIP(launch_const64(p->r, p->ndim, P, s));
+        SW_HIP(launch_const64(p->r, p->ndim, t.tx, t.nw, P, s));
         if (src.count) SW_HIP(launch_inject64(src, nxt, io->wavelet + size_t(n) * src.count, s));
         if (rec.count) SW_HIP(launch_record64(rec, nxt, io->traces + size_t(n) * rec.count, s));
         if (io->snaps && io->saving_stride > 0 && (n + 1) % io->saving_stride == 0)

@@ -152,11 +152,21 @@ __global__ void __launch_bounds__(64 * NW) k_const64(StencilParamsT<double> P)
 }
 
 template <int R>
-void launch_k_const64(int ndim, StencilParamsT<double> &P, hipStream_t s)
+hipError_t launch_k_const64(int ndim, int tx, int nw, StencilParamsT<double> &P, hipStream_t s)
 {
     const dim3 grid(P.ntx * P.nty * P.nzc);
-    if (ndim == 2) hipLaunchKernelGGL((k_const64<R, 2, 1, 1>), grid, dim3(64), 0, s, P);
-    else hipLaunchKernelGGL((k_const64<R, 3, kTile64X, kTile64W>), grid, dim3(64 * kTile64W), 0, s, P);
+    if (ndim == 2) {
+        hipLaunchKernelGGL((k_const64<R, 2, 1, 1>), grid, dim3(64), 0, s, P);
+        return hipGetLastError();
+    }
+#define SW_X(TXV, NWV)                                                                         \
+    if (tx == TXV && nw == NWV) {                                                              \
+        hipLaunchKernelGGL((k_const64<R, 3, TXV, NWV>), grid, dim3(64 * NWV), 0, s, P);        \
+        return hipGetLastError();                                                              \
+    }
+    SW_F64_SHAPES(SW_X)
+#undef SW_X
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -243,22 +253,21 @@ hipError_t launch_snapshot64(const Geom &g, const double *field, double *out, hi
     return hipGetLastError();
 }
 
-hipError_t launch_const64(int r, int ndim, StencilParamsT<double> &P, hipStream_t s)
+hipError_t launch_const64(int r, int ndim, int tx, int nw, StencilParamsT<double> &P, hipStream_t s)
 {
     switch (r) {
-    case 1: launch_k_const64<1>(ndim, P, s); break;
-    case 2: launch_k_const64<2>(ndim, P, s); break;
-    case 3: launch_k_const64<3>(ndim, P, s); break;
-    case 4: launch_k_const64<4>(ndim, P, s); break;
-    case 5: launch_k_const64<5>(ndim, P, s); break;
-    case 6: launch_k_const64<6>(ndim, P, s); break;
-    case 7: launch_k_const64<7>(ndim, P, s); break;
-    case 8: launch_k_const64<8>(ndim, P, s); break;
-    case 9: launch_k_const64<9>(ndim, P, s); break;
-    case 10: launch_k_const64<10>(ndim, P, s); break;
+    case 1: return launch_k_const64<1>(ndim, tx, nw, P, s);
+    case 2: return launch_k_const64<2>(ndim, tx, nw, P, s);
+    case 3: return launch_k_const64<3>(ndim, tx, nw, P, s);
+    case 4: return launch_k_const64<4>(ndim, tx, nw, P, s);
+    case 5: return launch_k_const64<5>(ndim, tx, nw, P, s);
+    case 6: return launch_k_const64<6>(ndim, tx, nw, P, s);
+    case 7: return launch_k_const64<7>(ndim, tx, nw, P, s);
+    case 8: return launch_k_const64<8>(ndim, tx, nw, P, s);
+    case 9: return launch_k_const64<9>(ndim, tx, nw, P, s);
+    case 10: return launch_k_const64<10>(ndim, tx, nw, P, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace sw

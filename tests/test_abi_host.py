@@ -302,8 +302,17 @@ def test_double_precision_contract():
     io = L.FwdIO()
     st = L.lib().sw_forward(p64._plan, ctypes.byref(io), None)
     assert L.STATUS[st] in ("SW_ERR_STATE", "SW_ERR_ARG")
+    # double precision takes its own tile shapes and a z chunk, nothing else
     _expect("SW_ERR_UNSUPPORTED", p64.set_tiling, 16, 4)
-    assert p64.tiling["tx"] == 8
+    _expect("SW_ERR_UNSUPPORTED", p64.set_tiling, 8, 8, ts=2)
+    _expect("SW_ERR_UNSUPPORTED", p64.set_tiling, 8, 8, occ=4)
+    assert (p64.tiling["tx"], p64.tiling["nw"]) == (8, 4)        # SO8 default
+    p64.set_tiling(16, 8, 9)
+    assert (p64.tiling["tx"], p64.tiling["nw"], p64.tiling["zc"]) == (16, 8, 9)
+    p64.set_tiling()
+    assert (p64.tiling["tx"], p64.tiling["nw"]) == (8, 4)
+    hi = Propagator((20, 24, 28), (10.0,) * 3, 12, 1e-4, 5, nbl=2, dtype="float64")
+    assert (hi.tiling["tx"], hi.tiling["nw"]) == (8, 8)
 
 
 def test_batch_tiling_contract():

@@ -78,3 +78,31 @@ def test_fp64_2d_free_surface_snapshots():
     assert res.snaps.shape[0] == 3
     for k in range(3):
         assert _rel(res.snaps[k].cpu().numpy(), ref.snaps[k]) < TOL64
+
+
+@pytest.mark.parametrize("so", [4, 20])
+def test_fp64_tile_shapes_are_bitwise_identical(so):
+    # every double-precision tile shape and chunk gives the same bits (ragged
+    # tiles along x and y, mirror sides), and agrees with the oracle
+    n = (33, 41, 75)
+    rng = np.random.default_rng(90 + so)
+    vel = workloads.layered(n, [1700.0, 2600.0], rng, 30.0).astype(np.float64)
+    h = (10.0, 10.0, 10.0)
+    src = np.array([[151.3, 201.7, 377.2]])
+    rec = np.array([[10.0, 9.0 * k, 5.0 * k + 1.3] for k in range(40)])
+    bc = (("neumann", "dirichlet"), ("dirichlet", "dirichlet"), ("dirichlet", "dirichlet"))
+    print(f"case: fp64 tile shapes SO{so}", flush=True)
+    ref, res, prop = _pair(n, h, so, [(0, 5), (4, 4), (3, 6)], bc, 90, vel, src, rec, "linear", "float64")
+    total, worst, _ = trace_errors(res.traces, ref.traces)
+    assert total < TOL64 and worst < TOL64, (total, worst)
+    u0 = prop.grid_view(res.fields[res.current]).clone()
+    tr0 = res.traces.clone()
+    wav = torch.from_numpy(oracle.ricker(16.0, prop.dt, 90)[:, None]).cuda()
+    for tx, nw, zc in [(16, 8, 0), (8, 4, 7), (24, 8, 13), (8, 8, 1)]:
+        print(f"case: fp64 SO{so} tile {tx}x{nw} zc={zc}", flush=True)
+        prop.set_tiling(tx, nw, zc)
+        r = prop.forward(wav)
+        torch.cuda.synchronize()
+        assert torch.equal(r.traces, tr0)
+        assert torch.equal(prop.grid_view(r.fields[r.current]), u0)
+    prop.set_tiling()
