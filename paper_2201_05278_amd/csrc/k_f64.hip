@@ -6,6 +6,7 @@
 #include "stencil_const.h"
 
 #include "device64.h"
+#include "ghost.h"
 
 namespace sw {
 
@@ -99,37 +100,6 @@ __global__ void __launch_bounds__(kBlock) k_record64(PointTable64 t, const doubl
         for (int e = t.ptr[pt] + sub; e < t.ptr[pt + 1]; e += G) acc += t.wscaled[e] * field[t.node[e]];
     acc = group_sum64<G>(acc);
     if (pt < t.count && sub == 0) out[pt] = acc;
-}
-
-// Mirror ghosts along one axis (Dirichlet odd, Neumann even), as in single
-// precision.
-__global__ void k_ghost64(Geom g, int axis, int lo, int hi, int depth, double *__restrict__ f)
-{
-    const int n[3] = {g.Z, g.X, g.Y};
-    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-    const int64_t rows = int64_t(n[a1]) * n[a2];
-    const int64_t total = rows * depth * 2;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t r = i % rows;
-        const int k = 1 + int((i / rows) % depth);
-        const int side = int(i / (rows * depth));
-        const int bc = side ? hi : lo;
-        if (bc == 0) continue;
-        int src[3] = {0, 0, 0}, dst[3] = {0, 0, 0};
-        src[a1] = dst[a1] = int(r / n[a2]);
-        src[a2] = dst[a2] = int(r % n[a2]);
-        if (side == 0) {
-            dst[axis] = -k;
-            src[axis] = k;
-        } else {
-            dst[axis] = n[axis] - 1 + k;
-            src[axis] = n[axis] - 1 - k;
-        }
-        if (src[axis] < 0 || src[axis] >= n[axis]) continue;
-        const double v = f[elem(g, src[0], src[1], src[2])];
-        f[elem(g, dst[0], dst[1], dst[2])] = bc == 1 ? -v : v;
-    }
 }
 
 __global__ void k_snapshot64(Geom g, const double *__restrict__ f, double *__restrict__ out)
@@ -233,17 +203,11 @@ hipError_t launch_record64(const PointTable64 &t, const double *field, double *o
 
 hipError_t launch_ghost64(const Geom &g, const int (*bcm)[2], int depth, double *field, hipStream_t s)
 {
-    const int n[3] = {g.Z, g.X, g.Y};
-    for (int axis = 0; axis < 3; ++axis) {
-        if (!bcm[axis][0] && !bcm[axis][1]) continue;
-        const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-        const int64_t total = int64_t(n[a1]) * n[a2] * depth * 2;
-        hipLaunchKernelGGL(k_ghost64, dim3(blocks_for64(total)), dim3(kBlock), 0, s, g, axis, bcm[axis][0],
-                           bcm[axis][1], depth, field);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const GhostSides sd = ghost_sides(g, bcm, depth);
+    const int64_t total = sd.items[0] + sd.items[1] + sd.items[2];
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_all<double>, dim3(blocks_for64(total)), dim3(kBlock), 0, s, g, sd, depth, field);
+    return hipGetLastError();
 }
 
 hipError_t launch_snapshot64(const Geom &g, const double *field, double *out, hipStream_t s)

@@ -7,6 +7,7 @@
 // give a group of G lanes (a power of two up to the wavefront width) to one
 // node or receiver and finish with a butterfly reduction inside the group.
 #include "device.h"
+#include "ghost.h"
 
 #include <mutex>
 
@@ -121,39 +122,6 @@ __global__ void k_model_prep(Geom g, Sides sd, int hz, int hx, int pz, int schem
             K[i] = m;
             aux[i] = rho[ph];
         }
-    }
-}
-
-// Mirror ghosts along one axis: thread i covers one (ghost layer, side, row of
-// the other two axes) item; ghost node at distance k outside the boundary node
-// takes sign * p at distance k inside it.
-__global__ void k_ghost_axis(Geom g, int axis, int lo, int hi, int depth, float *__restrict__ f)
-{
-    const int n[3] = {g.Z, g.X, g.Y};
-    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-    const int64_t rows = int64_t(n[a1]) * n[a2];
-    const int64_t total = rows * depth * 2;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t r = i % rows;
-        const int k = 1 + int((i / rows) % depth);
-        const int side = int(i / (rows * depth));
-        const int bc = side ? hi : lo;
-        if (bc == 0) continue;
-        const int c[3] = {0, 0, 0};
-        int src[3] = {c[0], c[1], c[2]}, dst[3] = {c[0], c[1], c[2]};
-        src[a1] = dst[a1] = int(r / n[a2]);
-        src[a2] = dst[a2] = int(r % n[a2]);
-        if (side == 0) {
-            dst[axis] = -k;
-            src[axis] = k;
-        } else {
-            dst[axis] = n[axis] - 1 + k;
-            src[axis] = n[axis] - 1 - k;
-        }
-        if (src[axis] < 0 || src[axis] >= n[axis]) continue;   // extent below the ghost depth
-        const float v = f[elem(g, src[0], src[1], src[2])];
-        f[elem(g, dst[0], dst[1], dst[2])] = bc == 1 ? -v : v;
     }
 }
 
@@ -393,17 +361,11 @@ hipError_t launch_count_nonfinite(const float *a, int64_t n, uint32_t *count, hi
 
 hipError_t launch_ghost_fill(const Geom &g, const int (*bcm)[2], int depth, float *field, hipStream_t s)
 {
-    const int n[3] = {g.Z, g.X, g.Y};
-    for (int axis = 0; axis < 3; ++axis) {
-        if (!bcm[axis][0] && !bcm[axis][1]) continue;
-        const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-        const int64_t total = int64_t(n[a1]) * n[a2] * depth * 2;
-        hipLaunchKernelGGL(k_ghost_axis, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, axis, bcm[axis][0],
-                           bcm[axis][1], depth, field);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const GhostSides sd = ghost_sides(g, bcm, depth);
+    const int64_t total = sd.items[0] + sd.items[1] + sd.items[2];
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_all<float>, dim3(blocks_for(total)), dim3(kBlock), 0, s, g, sd, depth, field);
+    return hipGetLastError();
 }
 
 hipError_t launch_point_coef(const PointTableDev &t, const float2 *damp, const float *vel, const float *rho_inj,
