@@ -973,6 +973,9 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
     // phi^{m+1} is still held (anxt) next to phi^m (acur); a step left over at
     // the end of a segment is formed alone
     auto u_level = [&](int m, int k) -> const float * { return io->segment + size_t(E + m - k) * fe; };
+    // constant density on block tiles: imaging steps in pairs (one gradient
+    // pass per two steps)
+    const bool pair_image = !vd && !choose_tiling(p).wt;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k = seg * E;
         const int L = std::min(E, N - k);
@@ -1000,6 +1003,7 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
         // adjoint steps m = top .. k (top = N in the last segment)
         const int top = (seg == nseg - 1) ? N : k + L - 1;
         int pend = -1;              // imaging step whose face term is deferred
+        int gpend = -1;             // constant density: step whose imaging term is deferred
         for (int m = top; m >= k; --m) {
             P.cur = acur;
             P.nxt = anxt;
@@ -1016,9 +1020,26 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
                     if (src.count)   // phi^{m+1} (acur, left unchanged by the step) at the sources
                         SW_HIP(launch_src_image(src, acur, io->wavelet + size_t(m) * src.count, src_sum, s));
                 }
-                P.store = io->segment + size_t(m - k) * fe;
-                P.grad = io->grad_m;
-                SW_HIP(stencil(p, MODE_IMAGE, P, s));
+                if (pair_image && gpend == m + 1) {
+                    // this step's imaging term and the one deferred from step m + 1:
+                    // phi^{m+2}, the p^{n-1} this launch reads, against that step's level
+                    P.store = io->segment + size_t(m - k) * fe;
+                    P.store2 = io->segment + size_t(m + 1 - k) * fe;
+                    P.grad = io->grad_m;
+                    SW_HIP(stencil(p, MODE_IMAGE2, P, s));
+                    gpend = -1;
+                } else if (pair_image && m > k) {
+                    // deferred to step m - 1 of this segment (the gradient is then
+                    // read and written once per two steps)
+                    P.store = nullptr;
+                    P.grad = nullptr;
+                    SW_HIP(stencil(p, MODE_FWD, P, s));
+                    gpend = m;
+                } else {
+                    P.store = io->segment + size_t(m - k) * fe;
+                    P.grad = io->grad_m;
+                    SW_HIP(stencil(p, MODE_IMAGE, P, s));
+                }
             } else {
                 P.store = nullptr;
                 P.grad = nullptr;

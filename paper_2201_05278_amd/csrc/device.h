@@ -23,7 +23,7 @@ __host__ __device__ inline int64_t elem(const Geom &g, int z, int x, int y)
     return g.origin + (int64_t(z) * g.px + x) * g.py + y;
 }
 
-enum StencilMode { MODE_FWD = 0, MODE_STORE = 1, MODE_IMAGE = 2 };
+enum StencilMode { MODE_FWD = 0, MODE_STORE = 1, MODE_IMAGE = 2, MODE_IMAGE2 = 3 };
 
 // Blocks are dealt round-robin to the 8 XCDs; remap the flat block index so
 // that each XCD receives a contiguous range of tiles (neighbouring tiles then
@@ -67,6 +67,7 @@ struct StencilParamsT {
     int ndamp;              // entries of damp
     T *store;               // MODE_STORE: K (L p) written; MODE_IMAGE: read
     T *grad;                // MODE_IMAGE: += p * store / K^2
+    T *store2;              // MODE_IMAGE2: the next step's stored level, imaged against p^{n-1}
     T *ustore;              // MODE_STORE, staggered scheme: p^n written (the level imaged by the face term)
     Geom g;
     T c0;                   // sum over axes of v_0 / h^2

@@ -22,7 +22,11 @@
 // Modes: MODE_FWD plain step; MODE_STORE also writes K (L p) (the recomputed
 // forward level of the imaging condition); MODE_IMAGE also accumulates
 // grad += p * store / K^2 (zero-lag imaging of the adjoint field p against the
-// stored level).
+// stored level); MODE_IMAGE2 also takes the imaging term of the next adjoint
+// step, deferred to this one, from the level p^{n-1} it reads anyway and the
+// next step's stored level: grad = p store / K^2 + (p^{n-1} store2 / K^2 +
+// grad), the two single steps' fused multiply-adds in their order, with the
+// gradient read and written once for both.
 #pragma once
 
 #include "device.h"
@@ -181,9 +185,11 @@ __device__ __forceinline__ void const_tile(const StencilParamsT<T> &P, int bid)
     const auto rn = buf_res(P.nxt + w0, wbytes);
     const auto rk = buf_res(P.K + w0, wbytes);
     const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * uint32_t(sizeof(T2)));
-    __amdgpu_buffer_rsrc_t rs = rk, rg = rk;
+    constexpr bool kImage = (MODE == MODE_IMAGE || MODE == MODE_IMAGE2);
+    __amdgpu_buffer_rsrc_t rs = rk, rg = rk, rs2 = rk;
     if constexpr (MODE != MODE_FWD) rs = buf_res(P.store + w0, wbytes);
-    if constexpr (MODE == MODE_IMAGE) rg = buf_res(P.grad + w0, wbytes);
+    if constexpr (kImage) rg = buf_res(P.grad + w0, wbytes);
+    if constexpr (MODE == MODE_IMAGE2) rs2 = buf_res(P.store2 + w0, wbytes);
     // byte offset of plane z in the window
     auto soff = [&](int z) -> int { return (z - zw) * pb; };
     // planes read from memory: grid planes and mirror ghost planes
@@ -256,7 +262,7 @@ __device__ __forceinline__ void const_tile(const StencilParamsT<T> &P, int bid)
     }
 
     struct Slot {
-        T f[RPT], p[RPT], k[RPT], d[RPT], g[RPT];
+        T f[RPT], p[RPT], k[RPT], d[RPT], g[RPT], d2[MODE == MODE_IMAGE2 ? RPT : 1];
         T2 ab[RPT];
         T hx[HXN > 0 ? HXN : 1], hy[YHN];
     };
@@ -279,10 +285,11 @@ __device__ __forceinline__ void const_tile(const StencilParamsT<T> &P, int bid)
             L.f[i] = keep_mask(buf_ldt<T, 0>(rc, rr[i], sf), fm);
             L.p[i] = buf_ldt<T, NT>(rn, ro[i], so);
             L.k[i] = buf_ldt<T, NT>(rk, ro[i], so);
-            if constexpr (MODE == MODE_IMAGE) {
+            if constexpr (kImage) {
                 L.d[i] = buf_ldt<T, NT>(rs, ro[i], so);
                 L.g[i] = buf_ldt<T, NT>(rg, ro[i], so);
             }
+            if constexpr (MODE == MODE_IMAGE2) L.d2[i] = buf_ldt<T, NT>(rs2, ro[i], so);
         }
 #pragma unroll
         for (int s = 0; s < HXN; ++s) L.hx[s] = buf_ldt<T, 0>(rc, hxo[s], so);
@@ -332,6 +339,10 @@ __device__ __forceinline__ void const_tile(const StencilParamsT<T> &P, int bid)
                     if constexpr (MODE == MODE_STORE) buf_stt<T, NT>(W.k[i] * lap, rs, ro[i], so);
                     if constexpr (MODE == MODE_IMAGE)
                         buf_stt<T, NT>(fmat(c, W.d[i] / (W.k[i] * W.k[i]), W.g[i]), rg, ro[i], so);
+                    if constexpr (MODE == MODE_IMAGE2) {
+                        const T k2 = W.k[i] * W.k[i];
+                        buf_stt<T, NT>(fmat(c, W.d[i] / k2, fmat(W.p[i], W.d2[i] / k2, W.g[i])), rg, ro[i], so);
+                    }
                 }
             }
         }
@@ -581,7 +592,9 @@ hipError_t launch_const_shape(int mode, int occ, StencilParams &P, hipStream_t s
     switch (mode) {
     case MODE_FWD: launch_const_mode<R, NDIM, TX, NW, MODE_FWD, NT, PF>(occ, P, s); break;
     case MODE_STORE: launch_const_mode<R, NDIM, TX, NW, MODE_STORE, NT, PF>(occ, P, s); break;
-    default: launch_const_mode<R, NDIM, TX, NW, MODE_IMAGE, NT, PF>(occ, P, s); break;
+    case MODE_IMAGE: launch_const_mode<R, NDIM, TX, NW, MODE_IMAGE, NT, PF>(occ, P, s); break;
+    case MODE_IMAGE2: launch_const_mode<R, NDIM, TX, NW, MODE_IMAGE2, NT, PF>(occ, P, s); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -596,7 +609,8 @@ hipError_t launch_wave_shape(int mode, StencilParams &P, hipStream_t s)
     switch (mode) {
     case MODE_FWD: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_FWD, NT>), grid, block, 0, s, P); break;
     case MODE_STORE: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_STORE, NT>), grid, block, 0, s, P); break;
-    default: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_IMAGE, NT>), grid, block, 0, s, P); break;
+    case MODE_IMAGE: hipLaunchKernelGGL((k_const_wave<R, NDIM, RW, NWB, MODE_IMAGE, NT>), grid, block, 0, s, P); break;
+    default: return hipErrorInvalidValue;       // the paired imaging step runs on block tiles
     }
     return hipGetLastError();
 }
