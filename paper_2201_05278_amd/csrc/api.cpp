@@ -315,7 +315,8 @@ hipError_t stencil(const sw_plan *p, int mode, StencilParams &P, hipStream_t s)
     // the staggered imaging stencil holds two more values per node than the
     // other modes: 8 x 4 tiles leave it 2 waves per SIMD, 8 x 8 tiles 4 (1.77
     // against 2.03 ms per launch at 592^3 SO8), so it takes 8 x 8 by default
-    if (mode == MODE_IMAGE && p->prob.scheme == SW_VD_STAGGERED && p->ndim == 3 && !p->tile_tx) {
+    if ((mode == MODE_IMAGE || mode == MODE_IMAGE2) && p->prob.scheme == SW_VD_STAGGERED && p->ndim == 3 &&
+        !p->tile_tx) {
         t.tx = 8;
         t.nw = 8;
     }
@@ -973,9 +974,8 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
     // phi^{m+1} is still held (anxt) next to phi^m (acur); a step left over at
     // the end of a segment is formed alone
     auto u_level = [&](int m, int k) -> const float * { return io->segment + size_t(E + m - k) * fe; };
-    // constant density on block tiles: imaging steps in pairs (one gradient
-    // pass per two steps)
-    const bool pair_image = !vd && !choose_tiling(p).wt;
+    // block tiles: imaging steps in pairs (one gradient pass per two steps)
+    const bool pair_image = !choose_tiling(p).wt;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k = seg * E;
         const int L = std::min(E, N - k);
@@ -1003,7 +1003,7 @@ sw_status sw_adjoint(sw_plan *p, const sw_adj_io *io, void *stream)
         // adjoint steps m = top .. k (top = N in the last segment)
         const int top = (seg == nseg - 1) ? N : k + L - 1;
         int pend = -1;              // imaging step whose face term is deferred
-        int gpend = -1;             // constant density: step whose imaging term is deferred
+        int gpend = -1;             // step whose imaging term is deferred
         for (int m = top; m >= k; --m) {
             P.cur = acur;
             P.nxt = anxt;

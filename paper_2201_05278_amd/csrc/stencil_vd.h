@@ -105,9 +105,15 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
     const auto rd = buf_res(P.damp, uint32_t(P.ndamp) * 8u);
     // imaging arrays share the wavefield layout and window
     __amdgpu_buffer_rsrc_t rs = rk, ru = rk, rg = rk;
+    // imaging modes: one term per step, or (MODE_IMAGE2) this step's and the
+    // next step's deferred term, from the p^{n-1} level read anyway and that
+    // step's stored level (the two single steps' fused multiply-adds in order)
+    constexpr bool kImage = (MODE == MODE_IMAGE || MODE == MODE_IMAGE2);
+    __amdgpu_buffer_rsrc_t rs2 = rk;
     if constexpr (MODE != MODE_FWD) rs = buf_res(P.store + w0, wbytes);
     if constexpr (MODE == MODE_STORE) ru = buf_res(P.ustore + w0, wbytes);
-    if constexpr (MODE == MODE_IMAGE) rg = buf_res(P.grad + w0, wbytes);
+    if constexpr (kImage) rg = buf_res(P.grad + w0, wbytes);
+    if constexpr (MODE == MODE_IMAGE2) rs2 = buf_res(P.store2 + w0, wbytes);
     auto soff = [&](int z) -> int { return (z - zw) * pb; };
     auto zmask = [&](int z) -> unsigned {
         return axis_read(z, g.Z, P.bcm[0][0], P.bcm[0][1], P.gh) ? ~0u : 0u;
@@ -194,7 +200,7 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
         float fp[RPT], fb[RPT], p[RPT], k[RPT];
         float2 ab[RPT];
         float hxp[HXN > 0 ? HXN : 1], hxb[HXN > 0 ? HXN : 1], hyp[YHN], hyb[YHN];
-        float d[MODE == MODE_IMAGE ? RPT : 1], gr[MODE == MODE_IMAGE ? RPT : 1];
+        float d[kImage ? RPT : 1], gr[kImage ? RPT : 1], d2[MODE == MODE_IMAGE2 ? RPT : 1];
     };
     // loads of plane z: the queue inputs p and b at z + 2R - 1, and for z >= zb
     // the plane's own p^{n-1}, K, (A, B) and the halos of p and b
@@ -215,10 +221,11 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
             L.p[i] = buf_ld<NT>(rn, ro[i], so);
             L.k[i] = buf_ld<NT>(rk, ro[i], so);
             L.ab[i] = buf_ld2(rd, (ez * ez + ex2[i]) * 8);
-            if constexpr (MODE == MODE_IMAGE) {
+            if constexpr (kImage) {
                 L.d[i] = buf_ld<NT>(rs, ro[i], so);
                 L.gr[i] = buf_ld<NT>(rg, ro[i], so);
             }
+            if constexpr (MODE == MODE_IMAGE2) L.d2[i] = buf_ld<NT>(rs2, ro[i], so);
         }
 #pragma unroll
         for (int s = 0; s < HXN; ++s) {
@@ -362,6 +369,10 @@ __global__ void __launch_bounds__(64 * NW) k_stag(StencilParams P)
                 }
                 if constexpr (MODE == MODE_IMAGE)
                     buf_st<NT>(fmaf(c, W.d[i] / (W.k[i] * W.k[i]), W.gr[i]), rg, ro[i], so);
+                if constexpr (MODE == MODE_IMAGE2) {
+                    const float k2 = W.k[i] * W.k[i];
+                    buf_st<NT>(fmaf(c, W.d[i] / k2, fmaf(W.p[i], W.d2[i] / k2, W.gr[i])), rg, ro[i], so);
+                }
             }
         }
     }
@@ -608,6 +619,7 @@ hipError_t launch_vd_shape(int scheme, int mode, int occ, StencilParams &P, hipS
     if (scheme == 1) {
         if (mode == MODE_STORE) launch_stag_mode<R, NDIM, TX, NW, NT, MODE_STORE>(occ, P, s);
         else if (mode == MODE_IMAGE) launch_stag_mode<R, NDIM, TX, NW, NT, MODE_IMAGE>(occ, P, s);
+        else if (mode == MODE_IMAGE2) launch_stag_mode<R, NDIM, TX, NW, NT, MODE_IMAGE2>(occ, P, s);
         else launch_stag_mode<R, NDIM, TX, NW, NT, MODE_FWD>(occ, P, s);
     } else {
         constexpr auto kern = k_cent<R, NDIM, TX, NW, NT>;
