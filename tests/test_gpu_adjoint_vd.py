@@ -182,3 +182,18 @@ def test_vd_zero_residual_gives_zero_gradients():
     gv, _, gK, gr = prop.adjoint(wt, torch.zeros_like(fw.traces), fw.ckpt, 7)
     torch.cuda.synchronize()
     assert not torch.any(gv) and not torch.any(gr) and not torch.any(gK)
+
+
+def test_vd_gradients_bitwise_over_checkpoint_intervals():
+    # checkpointing and the pairing of imaging steps (two terms per gradient
+    # pass, faces two steps per launch) keep every accumulation in step order:
+    # the gradients are the same bits for segments of 1 (nothing paired), odd
+    # and even lengths
+    n, so, nsteps, nbl = (24, 29, 66), 6, 45, 4
+    args = _case(n, so, nsteps, nbl, seed=8)
+    _, gv1, gr1, _, _ = _gpu_grads(n, so, nsteps, nbl, *args, every=1)
+    for every in (2, 7, 16, 45):
+        print(f"case: VD gradients, checkpoints every {every} against every 1", flush=True)
+        _, gv, gr, _, _ = _gpu_grads(n, so, nsteps, nbl, *args, every=every)
+        assert torch.equal(gv, gv1), every
+        assert torch.equal(gr, gr1), every
