@@ -26,6 +26,8 @@ Cases:
                     staggered operator runs at about 0.0025 Gpts/s here, so
                     the headline 512^3 grid is out of its reach), trilinear
                     source / receivers (every 10th row and column stored)
+  smooth200_cent    the same configuration with the centred variable-density
+                    operator (the paper's form), 400 steps
   gradient320       320^3 + layer layered + N(0, 50^2) model, 2 of the 8
                     shots, SO8, 300 steps, L2 misfit against data of the
                     unperturbed layered model; velocity gradient summed over
@@ -97,6 +99,15 @@ def case_smooth200_stag():
     subset = grid_subset(nside, 10)
     return {"dt": dt, "nsteps": STAG_STEPS, "subset": subset,
             "traces": _traces(wl, "vd_staggered", dt, STAG_STEPS, subset)}
+
+
+def case_smooth200_cent():
+    wl = workloads.smooth_3d(n=200, nsteps=STAG_STEPS, scheme="vd_centred")
+    dt = workloads.CFL_FRACTION * oracle.coeffs.critical_dt(wl.h, wl.space_order, wl.cmax)
+    nside = int(round(np.sqrt(len(wl.rec))))
+    subset = grid_subset(nside, 10)
+    return {"dt": dt, "nsteps": STAG_STEPS, "subset": subset,
+            "traces": _traces(wl, "vd_centred", dt, STAG_STEPS, subset)}
 
 
 def batch_pick(shots):

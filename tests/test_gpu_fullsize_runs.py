@@ -74,6 +74,14 @@ def test_smooth200_staggered_against_oracle():
     _check("smooth200_stag", tr[:, torch.from_numpy(g["subset"]).cuda()], g["traces"])
 
 
+def test_smooth200_centred_against_oracle():
+    g = _golden("smooth200_cent")
+    wl = workloads.smooth_3d(n=200, nsteps=int(g["nsteps"]), scheme="vd_centred")
+    print(f"case: smooth 200^3 centred VD, {int(g['nsteps'])} steps, all {len(wl.rec)} receivers", flush=True)
+    tr = _run(wl, "vd_centred", float(g["dt"]), int(g["nsteps"]))
+    _check("smooth200_cent", tr[:, torch.from_numpy(g["subset"]).cuda()], g["traces"])
+
+
 @pytest.mark.parametrize("scheme", ["const", "vd_staggered"])
 def test_smooth512_reciprocity_2000_steps(scheme):
     # The whole 2000-step run at the headline grid, where the oracle cannot
