@@ -360,8 +360,8 @@ sw_status sw_plan_set_tiling(sw_plan *plan, const sw_tiling *t);
 sw_status sw_plan_get_tiling(const sw_plan *plan, sw_tiling *out);
 /* Resident blocks per compute unit of the plan's stencil kernel under its
  * current tiling (the runtime's occupancy calculator) and the device's
- * compute units: set for 3D block tiles in single precision (every
- * scheme), 0 and 0 otherwise or without a device. */
+ * compute units: set for 3D block tiles (every scheme and precision), 0
+ * and 0 otherwise or without a device. */
 sw_status sw_plan_occupancy(const sw_plan *plan, int32_t *blocks_per_cu, int32_t *cus);
 
 /* ---- batched shots and autotuning --------------------------------------- */

@@ -44,5 +44,7 @@ hipError_t launch_record64(const PointTable64 &t, const double *field, double *o
 hipError_t launch_ghost64(const Geom &g, const int (*bcm)[2], int depth, double *field, hipStream_t s);
 hipError_t launch_snapshot64(const Geom &g, const double *field, double *out, hipStream_t s);
 hipError_t launch_const64(int r, int ndim, int tx, int nw, StencilParamsT<double> &P, hipStream_t s);
+// Resident blocks per CU of the 3D double-precision stencil of a tile shape (0: unknown).
+int f64_resident_blocks(int r, int tx, int nw);
 
 }  // namespace sw

@@ -217,6 +217,41 @@ hipError_t launch_snapshot64(const Geom &g, const double *field, double *out, hi
     return hipGetLastError();
 }
 
+template <int R, int TX, int NW>
+int resident64_shape()
+{
+    constexpr auto kern = k_const64<R, 3, TX, NW>;
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 64 * NW, 0) == hipSuccess ? n : 0;
+}
+
+template <int R>
+int resident64(int tx, int nw)
+{
+#define SW_X(TXV, NWV) \
+    if (tx == TXV && nw == NWV) return resident64_shape<R, TXV, NWV>();
+    SW_F64_SHAPES(SW_X)
+#undef SW_X
+    return 0;
+}
+
+int f64_resident_blocks(int r, int tx, int nw)
+{
+    switch (r) {
+    case 1: return resident64<1>(tx, nw);
+    case 2: return resident64<2>(tx, nw);
+    case 3: return resident64<3>(tx, nw);
+    case 4: return resident64<4>(tx, nw);
+    case 5: return resident64<5>(tx, nw);
+    case 6: return resident64<6>(tx, nw);
+    case 7: return resident64<7>(tx, nw);
+    case 8: return resident64<8>(tx, nw);
+    case 9: return resident64<9>(tx, nw);
+    case 10: return resident64<10>(tx, nw);
+    default: return 0;
+    }
+}
+
 hipError_t launch_const64(int r, int ndim, int tx, int nw, StencilParamsT<double> &P, hipStream_t s)
 {
     switch (r) {

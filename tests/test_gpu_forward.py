@@ -181,18 +181,19 @@ def test_capped_kernel_first_launched_inside_graph_capture():
     prop.set_tiling()
 
 
-@pytest.mark.parametrize("n,nbl,so,scheme", [((512,) * 3, 40, 8, "const"), ((207, 801, 801), 0, 8, "const"),
-                                             ((207, 801, 801), 0, 4, "const"), ((512,) * 3, 40, 12, "const"),
-                                             ((60, 70, 80), 4, 8, "const"), ((320,) * 3, 40, 8, "vd_staggered"),
-                                             ((256,) * 3, 40, 16, "vd_staggered"), ((320,) * 3, 40, 8, "vd_centred")])
-def test_default_chunk_follows_resident_rounds(n, nbl, so, scheme):
-    # the default z chunk of 3D block tiles, recomputed from its stated rule
+@pytest.mark.parametrize("n,nbl,so,scheme,dtype", [
+    ((512,) * 3, 40, 8, "const", "float32"), ((207, 801, 801), 0, 8, "const", "float32"),
+    ((207, 801, 801), 0, 4, "const", "float32"), ((512,) * 3, 40, 12, "const", "float32"),
+    ((60, 70, 80), 4, 8, "const", "float32"), ((320,) * 3, 40, 8, "vd_staggered", "float32"),
+    ((256,) * 3, 40, 16, "vd_staggered", "float32"), ((320,) * 3, 40, 8, "vd_centred", "float32")])
+def test_default_chunk_follows_resident_rounds(n, nbl, so, scheme, dtype):
+    # the default z chunk of 3D single-precision block tiles, recomputed from its stated rule
     # and the kernel's resident blocks (plans only, no device memory): the
     # chunk of 4R .. 100 planes with the fewest ceil(blocks / resident) *
     # (zc + 2R), ties to the shorter chunk, among chunks making at least three
     # rounds; else the fixed wave target
     import math
-    prop = Propagator(n, (10.0,) * 3, so, 1e-4, 5, nbl=nbl, scheme=scheme)
+    prop = Propagator(n, (10.0,) * 3, so, 1e-4, 5, nbl=nbl, scheme=scheme, dtype=dtype)
     t = prop.tiling
     res, cus = prop.occupancy
     print(f"case: default chunk {n} + {nbl} SO{so} {scheme}: tiling {t}, resident {res} x {cus}", flush=True)
